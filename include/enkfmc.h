@@ -1,0 +1,193 @@
+/*
+ * enkfmc.h -- C ABI of the MI355X EnKF-MC hot path.
+ *
+ * The library computes, for a background ensemble X_b (n x N), the analysis
+ * ensemble of the ensemble Kalman filter based on the modified Cholesky
+ * decomposition (arXiv 1606.00807):
+ *
+ *   - Section 3 / Alg. 2: the grid is split into Delta = sdx*sdy sub-domains,
+ *     each extended by a halo of r_h grid points;
+ *   - eq. (1), eq. (8), Alg. 3 first step: in every sub-domain each component's
+ *     ensemble anomalies are regressed on its predecessors inside its local box
+ *     of radius r (Section 2.3, text after eq. 9), giving B^-1 ~ T^T D^-1 T;
+ *   - eq. (11) per sub-domain (eq. 14, Alg. 3): the local analysis increment
+ *     solves (T^T D^-1 T + H^T R^-1 H) dX = H^T R^-1 (Y^s - H X_b);
+ *   - Alg. 2 merge step: interior rows are written back to the global grid.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Global ordering: variable-major, then level, then latitude, then
+ *    longitude (longitude fastest).  Component g = off_v + (lev*ny + lat)*nx + lon.
+ *  - Matrices are row-major with the N members of one component contiguous:
+ *    X_b and X_a are (n, N), Y^s is (m, N).
+ *  - H is a selection: obs_idx[o] is the component observed by observation o
+ *    (strictly increasing, inside [0, n)).  R is diagonal: r_diag[o] > 0.
+ *  - Sub-domain k = ky*sdx + kx.  Its local rows are ordered variable, level,
+ *    local latitude, local longitude over its extended box.  Predecessors are
+ *    same-variable rows earlier in that local order with |dlev| <= r_v,
+ *    |dlat| <= r_h, |dlon| <= r_h.  With sdx == 1 and a periodic grid there is
+ *    no longitude halo and longitude distance is periodic.
+ *  - Arguments named "dev" point to device memory, "host" to host memory.
+ *  - A stream argument is a hipStream_t passed as void* (NULL: null stream).
+ *    Every device call is ordered on that stream and ends with one small
+ *    device-to-host read of a status word, so it returns only after its work
+ *    has finished.
+ *  - No entry point throws.  On failure a negative status is returned and
+ *    enkfmc_last_error() describes it (per calling thread).
+ *  - A plan is not re-entrant: calls on one plan must not overlap.  Distinct
+ *    plans are independent.
+ */
+#ifndef ENKFMC_H
+#define ENKFMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ENKFMC_OK = 0,
+  ENKFMC_EINVAL = -1,       /* bad argument, geometry or observation list          */
+  ENKFMC_ENOTSPD = -2,      /* a regression or innovation matrix is not SPD        */
+  ENKFMC_ENONPOS_D = -3,    /* a residual variance D_ii is not positive            */
+  ENKFMC_ENOCONV = -4,      /* iterative solve did not converge within its limit   */
+  ENKFMC_EHIP = -5,         /* HIP runtime error                                   */
+  ENKFMC_ENOMEM = -6,       /* workspace too small or host allocation failed       */
+  ENKFMC_ESTATE = -7,       /* call out of order (e.g. analyze before fit)         */
+  ENKFMC_EUNSUPPORTED = -8  /* sizes beyond what the kernels were built for        */
+} enkfmc_status;
+
+typedef enum { ENKFMC_F32 = 0, ENKFMC_F64 = 1 } enkfmc_dtype;
+
+/* How enkfmc_fit computes the regressions (same result within rounding). */
+typedef enum {
+  ENKFMC_FIT_PLAIN = 0,   /* one workgroup per regression, FP64 vector arithmetic */
+  ENKFMC_FIT_BATCHED = 1  /* one wavefront per regression, FP64 MFMA Gram, register Cholesky */
+} enkfmc_fit_mode;
+
+/* How enkfmc_analyze solves the local systems (same result within rounding). */
+typedef enum {
+  ENKFMC_SOLVE_DUAL = 0   /* direct: dual form eqs. (12)-(13) per variable block  */
+} enkfmc_solver;
+
+typedef struct {
+  int32_t nx, ny;          /* horizontal grid; longitude fastest                     */
+  int32_t nvar;            /* number of variables                                    */
+  const int32_t *nlev;     /* host [nvar]: levels of each variable (>= 1)            */
+  int32_t periodic_x;      /* 1: longitude wraps                                     */
+  int32_t sdx, sdy;        /* sub-domain tiles in longitude and latitude             */
+  int32_t r_h, r_v;        /* radius of influence (horizontal, vertical)            */
+} enkfmc_geometry;
+
+typedef struct enkfmc_plan enkfmc_plan;
+
+typedef struct {
+  int64_t n;               /* state size                                             */
+  int64_t N;               /* ensemble size                                          */
+  int64_t m;               /* observations                                           */
+  int64_t n_subdomains;    /* Delta                                                  */
+  int64_t n_blocks;        /* (sub-domain, variable) blocks                          */
+  int64_t n_fit;           /* local rows over all sub-domains (regressions)          */
+  int64_t nnz;             /* strictly-lower entries of T over all sub-domains       */
+  int64_t m_local;         /* local observations over all sub-domains                */
+  int32_t max_p;           /* largest predecessor count                              */
+  int32_t max_block_rows;  /* largest block                                          */
+  int32_t max_block_obs;   /* most observations in one block                         */
+  int32_t reserved;
+  size_t workspace_bytes;  /* device workspace enkfmc_plan_set_workspace needs       */
+} enkfmc_plan_info;
+
+/* Build the decomposition of Section 3 (host only, no device work).
+ * g: geometry; N >= 2 members; obs_idx (host, m entries, strictly increasing,
+ * inside [0, n)).  On success *out owns the plan (enkfmc_plan_destroy). */
+enkfmc_status enkfmc_plan_create(enkfmc_plan **out, const enkfmc_geometry *g, int32_t N,
+                                 const int32_t *obs_idx, int32_t m);
+
+enkfmc_status enkfmc_plan_get_info(const enkfmc_plan *p, enkfmc_plan_info *info);
+
+/* Hand the plan caller-owned device memory of at least info.workspace_bytes
+ * (256-byte aligned) and upload the index maps into it.  The plan keeps the
+ * pointer; the caller keeps the memory alive until the plan is destroyed or
+ * given another workspace. */
+enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes, void *stream);
+
+/* Fit B^-1 = T^T D^-1 T in every sub-domain (eq. 1, eq. 8; Alg. 3 first step).
+ * Xb: dev (n x N), element type dtype, row stride ld >= N elements.
+ * ridge >= 0 is added to the (N-1)-normalised Gram of every regression; with
+ * ridge == 0 a regression with N - 1 or more predecessors is ENOTSPD.
+ * mode: enkfmc_fit_mode.  T and D stay in the workspace.
+ * Errors: EINVAL, ESTATE (no workspace), ENOTSPD, ENONPOS_D, EHIP. */
+enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t ld, double ridge,
+                         int32_t mode, void *stream);
+
+/* Local analyses and merge (eq. 10, eq. 11 per sub-domain / eq. 14, Alg. 2-3).
+ * Needs the immediately preceding enkfmc_fit on the same X_b.
+ * Xb: dev (n x N, dtype, ld); Y: dev (m x N) float64 perturbed observations;
+ * r_diag: dev (m) float64 > 0; Xa: dev (n x N) contiguous, element type
+ * out_dtype.  The local increments of all rows stay in the workspace for
+ * enkfmc_analyze_backward.  Errors: EINVAL, ESTATE, ENOTSPD, EHIP. */
+enkfmc_status enkfmc_analyze(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t ld, const double *Y,
+                             const double *r_diag, void *Xa, int32_t out_dtype, int32_t solver, void *stream);
+
+/* Reverse-mode derivative of fit + analysis.  Given dXa = dL/dX_a (dev, n x N
+ * float64) it writes dL/dX_b (dev, n x N float64, overwritten), dL/dlog r
+ * (dev, m float64, overwritten) and dL/dridge (dev, 1 float64, overwritten).
+ * Needs the immediately preceding enkfmc_fit + enkfmc_analyze on the same
+ * inputs (same Xb, Y, r_diag, ridge), else ESTATE.  Recomputes each
+ * regression's Gram and factor instead of storing them.  Sums over the
+ * overlapping halos in a fixed order, so results are bitwise repeatable. */
+enkfmc_status enkfmc_analyze_backward(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t ld, const double *Y,
+                                      const double *r_diag, const double *dXa, double *dXb, double *dlogR,
+                                      double *dridge, void *stream);
+
+/* Parity exports of sub-domain k (host copies, local numbering of Section 3).
+ * Sizes first, then the arrays (any pointer may be NULL to skip it):
+ *  loc2glob[n_sd]   global component of each local row
+ *  interior[n_sd]   1 if the row is mapped back (not halo)
+ *  row_ptr[n_sd+1]  CSR of the strictly-lower pattern of T
+ *  col_idx[nnz_sd]  local predecessor rows, ascending within a row
+ *  obs[m_sd]        observation numbers o inside the extended box, ascending
+ *  obs_row[m_sd]    local row of each of them */
+enkfmc_status enkfmc_get_pattern_sizes(const enkfmc_plan *p, int32_t k, int64_t *n_sd, int64_t *nnz_sd,
+                                       int64_t *m_sd);
+enkfmc_status enkfmc_get_pattern(const enkfmc_plan *p, int32_t k, int64_t *loc2glob, uint8_t *interior,
+                                 int64_t *row_ptr, int32_t *col_idx, int32_t *obs, int32_t *obs_row);
+
+/* Fitted factors of sub-domain k after enkfmc_fit (host copies): tval[nnz_sd]
+ * = T values (= -beta) in the CSR order of enkfmc_get_pattern, d[n_sd] = D. */
+enkfmc_status enkfmc_get_factors(enkfmc_plan *p, int32_t k, double *tval, double *d, void *stream);
+
+/* Local increments Z (host, n_sd x N) of sub-domain k after enkfmc_analyze,
+ * halo rows included. */
+enkfmc_status enkfmc_get_increment(enkfmc_plan *p, int32_t k, double *Z, void *stream);
+
+/* Per-phase kernel timing (HIP events recorded on the call's stream around
+ * each kernel).  enable != 0 turns it on for later calls; enkfmc_get_timing
+ * returns the duration in ms of phase `phase` in the most recent call that
+ * ran it (0 if none).  Phases: */
+enum {
+  ENKFMC_PH_ANOMALY = 0,   /* mean and anomalies, eq. (5)                          */
+  ENKFMC_PH_FIT = 1,       /* regressions, eq. (1)                                 */
+  ENKFMC_PH_DUAL_F = 2,    /* F = T^-T H^T                                         */
+  ENKFMC_PH_DUAL_S = 3,    /* S = R + F^T D F                                      */
+  ENKFMC_PH_DUAL_CHOL = 4, /* Cholesky of S                                        */
+  ENKFMC_PH_DUAL_Q = 5,    /* Q = S^-1 (Y^s - H X_b)                               */
+  ENKFMC_PH_DUAL_G = 6,    /* D (F Q)                                              */
+  ENKFMC_PH_SWEEP = 7,     /* Z = T^-1 (...)                                       */
+  ENKFMC_PH_MAPBACK = 8,   /* X_a = X_b + Z on interior rows                       */
+  ENKFMC_PH_BACKWARD = 9,  /* whole reverse pass                                   */
+  ENKFMC_PH_COUNT = 16
+};
+enkfmc_status enkfmc_set_timing(enkfmc_plan *p, int32_t enable);
+enkfmc_status enkfmc_get_timing(const enkfmc_plan *p, int32_t phase, double *ms);
+
+const char *enkfmc_status_string(int32_t status);
+const char *enkfmc_last_error(void);
+void enkfmc_plan_destroy(enkfmc_plan *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ENKFMC_H */

@@ -1,0 +1,329 @@
+// C ABI entry points (include/enkfmc.h).
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "device.h"
+
+using namespace enkfmc;
+
+static thread_local std::string g_err;
+
+static enkfmc_status fail(enkfmc_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+static enkfmc_status hip_fail(hipError_t e, const char *where) {
+  return fail(ENKFMC_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, where)                 \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+// Read back the device status word (the one device->host read of each call).
+static enkfmc_status finish(enkfmc_plan *p, hipStream_t s, const char *what) {
+  int32_t st[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(st, p->ws + p->lay.status, sizeof(st), hipMemcpyDeviceToHost, s), what);
+  HIPCHK(hipStreamSynchronize(s), what);
+  if (p->timing) {
+    for (int ph = 0; ph < ENKFMC_PH_COUNT; ++ph) {
+      if (!(p->recorded & (uint64_t(1) << ph))) continue;
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, (hipEvent_t)p->ev[2 * ph], (hipEvent_t)p->ev[2 * ph + 1]), what);
+      p->phase_ms[ph] = ms;
+    }
+    p->recorded = 0;
+  }
+  if (st[0] != 0) {
+    std::string where;
+    if (st[1] >= 0) where = " (fit row " + std::to_string(st[1]) + ")";
+    else where = " (block " + std::to_string(-1 - st[1]) + ")";
+    const char *why = st[0] == ENKFMC_ENOTSPD ? "matrix not positive definite"
+                      : st[0] == ENKFMC_ENONPOS_D ? "residual variance not positive"
+                                                  : "device error";
+    return fail((enkfmc_status)st[0], std::string(what) + ": " + why + where);
+  }
+  return ENKFMC_OK;
+}
+
+static enkfmc_status begin(enkfmc_plan *p, hipStream_t s, const char *what) {
+  if (!p->ws) return fail(ENKFMC_ESTATE, std::string(what) + ": no workspace (call enkfmc_plan_set_workspace)");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev), what);
+  if (dev != p->device) return fail(ENKFMC_ESTATE, std::string(what) + ": current device differs from the workspace's");
+  HIPCHK(hipMemsetAsync(p->ws + p->lay.status, 0, 64, s), what);
+  return ENKFMC_OK;
+}
+
+template <typename T>
+static hipError_t put(enkfmc_plan *p, size_t off, const std::vector<T> &v, hipStream_t s) {
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(p->ws + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+extern "C" {
+
+enkfmc_status enkfmc_plan_create(enkfmc_plan **out, const enkfmc_geometry *g, int32_t N, const int32_t *obs_idx,
+                                 int32_t m) {
+  if (!out) return fail(ENKFMC_EINVAL, "out is NULL");
+  *out = nullptr;
+  enkfmc_plan *p = new (std::nothrow) enkfmc_plan();
+  if (!p) return fail(ENKFMC_ENOMEM, "plan allocation failed");
+  std::string err;
+  enkfmc_status st;
+  try {
+    st = build_plan(p, g, N, obs_idx, m, &err);
+  } catch (const std::bad_alloc &) {
+    st = ENKFMC_ENOMEM;
+    err = "host allocation failed while building the plan";
+  }
+  if (st != ENKFMC_OK) {
+    delete p;
+    return fail(st, "plan_create: " + err);
+  }
+  *out = p;
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_plan_get_info(const enkfmc_plan *p, enkfmc_plan_info *info) {
+  if (!p || !info) return fail(ENKFMC_EINVAL, "plan_get_info: NULL argument");
+  info->n = p->n;
+  info->N = p->N;
+  info->m = p->m;
+  info->n_subdomains = (int64_t)p->subs.size();
+  info->n_blocks = (int64_t)p->blocks.size();
+  info->n_fit = p->n_fit;
+  info->nnz = p->nnz;
+  info->m_local = p->m_local;
+  info->max_p = p->max_p;
+  info->max_block_rows = p->max_bn;
+  info->max_block_obs = p->max_bm;
+  info->reserved = 0;
+  info->workspace_bytes = p->lay.total;
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes, void *stream) {
+  if (!p || !dev) return fail(ENKFMC_EINVAL, "set_workspace: NULL argument");
+  if ((reinterpret_cast<uintptr_t>(dev) & 255) != 0) return fail(ENKFMC_EINVAL, "set_workspace: not 256-byte aligned");
+  if (bytes < p->lay.total)
+    return fail(ENKFMC_ENOMEM, "set_workspace: need " + std::to_string(p->lay.total) + " bytes, got " +
+                                   std::to_string(bytes));
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipGetDevice(&p->device), "set_workspace");
+  p->ws = (char *)dev;
+  p->ws_bytes = bytes;
+  p->fitted = p->analyzed = 0;
+  const Layout &L = p->lay;
+  HIPCHK(hipMemcpyAsync(p->ws + L.blocks, p->blocks.data(), p->blocks.size() * sizeof(Block), hipMemcpyHostToDevice, s),
+         "set_workspace");
+  HIPCHK(put(p, L.fit_glob, p->fit_glob, s), "set_workspace");
+  HIPCHK(put(p, L.fit_blk, p->fit_blk, s), "set_workspace");
+  HIPCHK(put(p, L.row_ptr, p->row_ptr, s), "set_workspace");
+  HIPCHK(put(p, L.col, p->col, s), "set_workspace");
+  HIPCHK(put(p, L.csc_ptr, p->csc_ptr, s), "set_workspace");
+  HIPCHK(put(p, L.csc_row, p->csc_row, s), "set_workspace");
+  HIPCHK(put(p, L.csc_nz, p->csc_nz, s), "set_workspace");
+  HIPCHK(put(p, L.interior_src, p->interior_src, s), "set_workspace");
+  HIPCHK(put(p, L.bobs_o, p->bobs_o, s), "set_workspace");
+  HIPCHK(put(p, L.bobs_row, p->bobs_row, s), "set_workspace");
+  HIPCHK(put(p, L.g2f_ptr, p->g2f_ptr, s), "set_workspace");
+  HIPCHK(put(p, L.g2f, p->g2f, s), "set_workspace");
+  HIPCHK(put(p, L.o2b_ptr, p->o2b_ptr, s), "set_workspace");
+  HIPCHK(put(p, L.o2b, p->o2b, s), "set_workspace");
+  HIPCHK(hipStreamSynchronize(s), "set_workspace");
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t ld, double ridge, int32_t mode,
+                         void *stream) {
+  if (!p || !Xb) return fail(ENKFMC_EINVAL, "fit: NULL argument");
+  if (dtype != ENKFMC_F32 && dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "fit: bad dtype");
+  if (ld < p->N) return fail(ENKFMC_EINVAL, "fit: ld < N");
+  if (!(ridge >= 0.0) || ridge > 1e300) return fail(ENKFMC_EINVAL, "fit: ridge must be finite and >= 0");
+  if (mode != ENKFMC_FIT_PLAIN && mode != ENKFMC_FIT_BATCHED) return fail(ENKFMC_EINVAL, "fit: bad mode");
+  hipStream_t s = (hipStream_t)stream;
+  enkfmc_status st = begin(p, s, "fit");
+  if (st != ENKFMC_OK) return st;
+  p->fitted = p->analyzed = 0;
+  const Dev d = make_dev(p);
+  HIPCHK(launch_anomaly(p, d, Xb, dtype, ld, s), "fit: anomaly launch");
+  if (mode == ENKFMC_FIT_PLAIN) {
+    if ((size_t)p->N * p->N * 8 + 8 * 1024 > 160 * 1024)
+      return fail(ENKFMC_EUNSUPPORTED, "fit: plain mode keeps an N x N Gram in LDS; N too large");
+    HIPCHK(launch_fit_plain(p, d, ridge, s), "fit: plain launch");
+  } else {
+    HIPCHK(launch_fit_batched(p, d, ridge, s), "fit: batched launch");
+  }
+  st = finish(p, s, "fit");
+  if (st != ENKFMC_OK) return st;
+  p->fitted = 1;
+  p->fit_ridge = ridge;
+  p->fit_xb = Xb;
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_analyze(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t ld, const double *Y,
+                             const double *r_diag, void *Xa, int32_t out_dtype, int32_t solver, void *stream) {
+  if (!p || !Xb || !Xa || (p->m > 0 && (!Y || !r_diag))) return fail(ENKFMC_EINVAL, "analyze: NULL argument");
+  if (dtype != ENKFMC_F32 && dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "analyze: bad dtype");
+  if (out_dtype != ENKFMC_F32 && out_dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "analyze: bad out_dtype");
+  if (ld < p->N) return fail(ENKFMC_EINVAL, "analyze: ld < N");
+  if (solver != ENKFMC_SOLVE_DUAL) return fail(ENKFMC_EINVAL, "analyze: unknown solver");
+  if (!p->fitted || p->fit_xb != Xb) return fail(ENKFMC_ESTATE, "analyze: needs the preceding fit on the same X_b");
+  hipStream_t s = (hipStream_t)stream;
+  enkfmc_status st = begin(p, s, "analyze");
+  if (st != ENKFMC_OK) return st;
+  p->analyzed = 0;
+  const Dev d = make_dev(p);
+  HIPCHK(launch_analysis_dual(p, d, Xb, dtype, ld, Y, r_diag, Xa, out_dtype, s), "analyze: launch");
+  st = finish(p, s, "analyze");
+  if (st != ENKFMC_OK) return st;
+  p->analyzed = 1;
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_analyze_backward(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t ld, const double *Y,
+                                      const double *r_diag, const double *dXa, double *dXb, double *dlogR,
+                                      double *dridge, void *stream) {
+  if (!p || !Xb || !dXa || !dXb || !dridge || (p->m > 0 && (!Y || !r_diag || !dlogR)))
+    return fail(ENKFMC_EINVAL, "analyze_backward: NULL argument");
+  if (dtype != ENKFMC_F32 && dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "analyze_backward: bad dtype");
+  if (ld < p->N) return fail(ENKFMC_EINVAL, "analyze_backward: ld < N");
+  if (!p->fitted || !p->analyzed || p->fit_xb != Xb)
+    return fail(ENKFMC_ESTATE, "analyze_backward: needs the preceding fit + analyze on the same inputs");
+  hipStream_t s = (hipStream_t)stream;
+  enkfmc_status st = begin(p, s, "analyze_backward");
+  if (st != ENKFMC_OK) return st;
+  const Dev d = make_dev(p);
+  HIPCHK(launch_backward(p, d, Xb, dtype, ld, Y, r_diag, p->fit_ridge, dXa, dXb, dlogR, dridge, s),
+         "analyze_backward: launch");
+  return finish(p, s, "analyze_backward");
+}
+
+enkfmc_status enkfmc_get_pattern_sizes(const enkfmc_plan *p, int32_t k, int64_t *n_sd, int64_t *nnz_sd,
+                                       int64_t *m_sd) {
+  if (!p || k < 0 || k >= (int32_t)p->subs.size()) return fail(ENKFMC_EINVAL, "get_pattern_sizes: bad sub-domain");
+  const SubBox &sb = p->subs[k];
+  int64_t ms = 0;
+  for (int32_t v = 0; v < p->nvar; ++v) ms += p->blocks[sb.blk0 + v].m;
+  if (n_sd) *n_sd = sb.n_sd;
+  if (nnz_sd) *nnz_sd = sb.nnz_sd;
+  if (m_sd) *m_sd = ms;
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_get_pattern(const enkfmc_plan *p, int32_t k, int64_t *loc2glob, uint8_t *interior,
+                                 int64_t *row_ptr, int32_t *col_idx, int32_t *obs, int32_t *obs_row) {
+  if (!p || k < 0 || k >= (int32_t)p->subs.size()) return fail(ENKFMC_EINVAL, "get_pattern: bad sub-domain");
+  const SubBox &sb = p->subs[k];
+  const Block &B0 = p->blocks[sb.blk0];
+  int64_t nzo = 0, mo = 0;
+  if (row_ptr) row_ptr[0] = 0;
+  for (int32_t v = 0; v < p->nvar; ++v) {
+    const Block &B = p->blocks[sb.blk0 + v];
+    for (int32_t i = 0; i < B.n; ++i) {
+      const int64_t r = B.row0 + i;
+      const int64_t li = B.sd_row0 + i;
+      if (loc2glob) loc2glob[li] = p->fit_glob[r];
+      if (interior) interior[li] = (uint8_t)(p->interior_src[p->fit_glob[r]] == r);
+      for (int64_t t = p->row_ptr[r]; t < p->row_ptr[r + 1]; ++t) {
+        if (col_idx) col_idx[nzo] = B.sd_row0 + p->col[t];
+        ++nzo;
+      }
+      if (row_ptr) row_ptr[li + 1] = nzo;
+    }
+    for (int32_t a = 0; a < B.m; ++a) {
+      if (obs) obs[mo] = p->bobs_o[B.obs0 + a];
+      if (obs_row) obs_row[mo] = B.sd_row0 + p->bobs_row[B.obs0 + a];
+      ++mo;
+    }
+  }
+  (void)B0;
+  // observations of a sub-domain are listed variable by variable above; the
+  // export orders them by observation number like the paper's local H.
+  if (obs && obs_row && mo > 1) {
+    std::vector<std::pair<int32_t, int32_t>> t(mo);
+    for (int64_t a = 0; a < mo; ++a) t[a] = {obs[a], obs_row[a]};
+    std::sort(t.begin(), t.end());
+    for (int64_t a = 0; a < mo; ++a) { obs[a] = t[a].first; obs_row[a] = t[a].second; }
+  }
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_get_factors(enkfmc_plan *p, int32_t k, double *tval, double *d, void *stream) {
+  if (!p || k < 0 || k >= (int32_t)p->subs.size()) return fail(ENKFMC_EINVAL, "get_factors: bad sub-domain");
+  if (!p->fitted) return fail(ENKFMC_ESTATE, "get_factors: no fit yet");
+  hipStream_t s = (hipStream_t)stream;
+  const SubBox &sb = p->subs[k];
+  const Block &B0 = p->blocks[sb.blk0];
+  const Dev dv = make_dev(p);
+  if (tval && sb.nnz_sd > 0)
+    HIPCHK(hipMemcpyAsync(tval, dv.tval + B0.nz0, sb.nnz_sd * 8, hipMemcpyDeviceToHost, s), "get_factors");
+  if (d) HIPCHK(hipMemcpyAsync(d, dv.dvec + B0.row0, sb.n_sd * 8, hipMemcpyDeviceToHost, s), "get_factors");
+  HIPCHK(hipStreamSynchronize(s), "get_factors");
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_get_increment(enkfmc_plan *p, int32_t k, double *Z, void *stream) {
+  if (!p || !Z || k < 0 || k >= (int32_t)p->subs.size()) return fail(ENKFMC_EINVAL, "get_increment: bad argument");
+  if (!p->analyzed) return fail(ENKFMC_ESTATE, "get_increment: no analysis yet");
+  hipStream_t s = (hipStream_t)stream;
+  const SubBox &sb = p->subs[k];
+  const Block &B0 = p->blocks[sb.blk0];
+  const Dev dv = make_dev(p);
+  HIPCHK(hipMemcpyAsync(Z, dv.Z + B0.row0 * p->N, sb.n_sd * p->N * 8, hipMemcpyDeviceToHost, s), "get_increment");
+  HIPCHK(hipStreamSynchronize(s), "get_increment");
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_set_timing(enkfmc_plan *p, int32_t enable) {
+  if (!p) return fail(ENKFMC_EINVAL, "set_timing: NULL plan");
+  if (enable && !p->ev[0]) {
+    for (int i = 0; i < 2 * ENKFMC_PH_COUNT; ++i) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e), "set_timing");
+      p->ev[i] = (void *)e;
+    }
+  }
+  p->timing = enable ? 1 : 0;
+  p->recorded = 0;
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_get_timing(const enkfmc_plan *p, int32_t phase, double *ms) {
+  if (!p || !ms || phase < 0 || phase >= ENKFMC_PH_COUNT) return fail(ENKFMC_EINVAL, "get_timing: bad argument");
+  *ms = p->phase_ms[phase];
+  return ENKFMC_OK;
+}
+
+const char *enkfmc_status_string(int32_t st) {
+  switch (st) {
+    case ENKFMC_OK: return "ENKFMC_OK";
+    case ENKFMC_EINVAL: return "ENKFMC_EINVAL";
+    case ENKFMC_ENOTSPD: return "ENKFMC_ENOTSPD";
+    case ENKFMC_ENONPOS_D: return "ENKFMC_ENONPOS_D";
+    case ENKFMC_ENOCONV: return "ENKFMC_ENOCONV";
+    case ENKFMC_EHIP: return "ENKFMC_EHIP";
+    case ENKFMC_ENOMEM: return "ENKFMC_ENOMEM";
+    case ENKFMC_ESTATE: return "ENKFMC_ESTATE";
+    case ENKFMC_EUNSUPPORTED: return "ENKFMC_EUNSUPPORTED";
+    default: return "ENKFMC_UNKNOWN";
+  }
+}
+
+const char *enkfmc_last_error(void) { return g_err.c_str(); }
+
+void enkfmc_plan_destroy(enkfmc_plan *p) {
+  if (!p) return;
+  for (int i = 0; i < 64; ++i)
+    if (p->ev[i]) hipEventDestroy((hipEvent_t)p->ev[i]);
+  delete p;
+}
+
+}  // extern "C"

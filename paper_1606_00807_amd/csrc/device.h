@@ -1,0 +1,106 @@
+// Device-side view of the workspace and small helpers shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace enkfmc {
+
+struct Dev {
+  const Block *blocks;
+  const int32_t *fit_glob, *fit_blk;
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const int64_t *csc_ptr;
+  const int32_t *csc_row, *csc_nz;
+  const int32_t *interior_src, *bobs_o, *bobs_row;
+  const int64_t *g2f_ptr;
+  const int32_t *g2f;
+  const int64_t *o2b_ptr;
+  const int32_t *o2b;
+  double *tval, *dvec, *mean, *U, *Z, *F, *S, *Q, *W, *aux1, *aux2, *aux3, *red;
+  int32_t *status;
+};
+
+inline Dev make_dev(enkfmc_plan *p) {
+  char *w = p->ws;
+  const Layout &L = p->lay;
+  Dev d;
+  d.blocks = (const Block *)(w + L.blocks);
+  d.fit_glob = (const int32_t *)(w + L.fit_glob);
+  d.fit_blk = (const int32_t *)(w + L.fit_blk);
+  d.row_ptr = (const int64_t *)(w + L.row_ptr);
+  d.col = (const int32_t *)(w + L.col);
+  d.csc_ptr = (const int64_t *)(w + L.csc_ptr);
+  d.csc_row = (const int32_t *)(w + L.csc_row);
+  d.csc_nz = (const int32_t *)(w + L.csc_nz);
+  d.interior_src = (const int32_t *)(w + L.interior_src);
+  d.bobs_o = (const int32_t *)(w + L.bobs_o);
+  d.bobs_row = (const int32_t *)(w + L.bobs_row);
+  d.g2f_ptr = (const int64_t *)(w + L.g2f_ptr);
+  d.g2f = (const int32_t *)(w + L.g2f);
+  d.o2b_ptr = (const int64_t *)(w + L.o2b_ptr);
+  d.o2b = (const int32_t *)(w + L.o2b);
+  d.tval = (double *)(w + L.tval);
+  d.dvec = (double *)(w + L.dvec);
+  d.mean = (double *)(w + L.mean);
+  d.U = (double *)(w + L.U);
+  d.Z = (double *)(w + L.Z);
+  d.F = (double *)(w + L.F);
+  d.S = (double *)(w + L.S);
+  d.Q = (double *)(w + L.Q);
+  d.W = (double *)(w + L.W);
+  d.aux1 = (double *)(w + L.aux1);
+  d.aux2 = (double *)(w + L.aux2);
+  d.aux3 = (double *)(w + L.aux3);
+  d.red = (double *)(w + L.red);
+  d.status = (int32_t *)(w + L.status);
+  return d;
+}
+
+// First error wins; status[1] records where it happened.
+__device__ inline void set_error(int32_t *status, int32_t code, int32_t where) {
+  if (atomicCAS(status, 0, code) == 0) atomicExch(status + 1, where);
+}
+
+// Sum over a 64-lane wavefront; every lane gets the same, order-fixed result.
+__device__ inline double wave_sum(double s) {
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
+// Sum over a 256-thread workgroup (red: >= 4 doubles of LDS).  Order-fixed.
+__device__ inline double block_sum256(double s, double *red) {
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+template <typename T> __device__ inline double ld_as_double(const T *p) { return (double)(*p); }
+
+// Phase timing: records a HIP event pair around a kernel when the plan asks for it.
+inline void phase_begin(enkfmc_plan *p, int ph, hipStream_t s) {
+  if (!p->timing) return;
+  hipEventRecord((hipEvent_t)p->ev[2 * ph], s);
+}
+inline void phase_end(enkfmc_plan *p, int ph, hipStream_t s) {
+  if (!p->timing) return;
+  hipEventRecord((hipEvent_t)p->ev[2 * ph + 1], s);
+  p->recorded |= (uint64_t(1) << ph);
+}
+
+// Host-side launchers (defined in the .hip files).
+hipError_t launch_anomaly(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, hipStream_t s);
+hipError_t launch_fit_plain(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
+hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
+hipError_t launch_analysis_dual(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld,
+                                const double *Y, const double *r_diag, void *Xa, int32_t out_dtype, hipStream_t s);
+hipError_t launch_backward(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, const double *Y,
+                           const double *r_diag, double lam, const double *dXa, double *dXb, double *dlogR,
+                           double *dridge, hipStream_t s);
+
+}  // namespace enkfmc

@@ -1,0 +1,87 @@
+// Internal plan of the EnKF-MC library: host decomposition + device layout.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/enkfmc.h"
+
+namespace enkfmc {
+
+// One (sub-domain, variable) block.  T, D and the local system are
+// block-diagonal per variable, so the block is the unit of every solve.
+struct Block {
+  int32_t sd, var;       // sub-domain, variable
+  int32_t nlev, BY, BX;  // local box: levels x latitudes x longitudes
+  int32_t n;             // rows = nlev*BY*BX
+  int32_t m;             // observations inside the block
+  int32_t sd_row0;       // first row of the block in its sub-domain's local order
+  int64_t row0;          // first fit row (global fit numbering)
+  int64_t nz0;           // first CSR entry of the block
+  int64_t obs0;          // first entry of the block's observation list
+  int64_t F0;            // offset of the block's F = T^-T H^T (n x m, row-major)
+  int64_t S0;            // offset of the block's m x m innovation matrix
+  int64_t Q0;            // offset of the block's m x N solve
+};
+
+struct SubBox {
+  int32_t kx, ky, x0, x1, y0, y1, xs, BX, ys, BY, ring;
+  int32_t blk0;          // first block of the sub-domain
+  int64_t n_sd, nnz_sd, m_sd;
+};
+
+// Offsets (bytes) of every device array inside the workspace.
+struct Layout {
+  size_t blocks, fit_glob, fit_blk, row_ptr, col, csc_ptr, csc_row, csc_nz, interior_src, bobs_o, bobs_row;
+  size_t g2f_ptr, g2f, o2b_ptr, o2b;
+  size_t tval, dvec, mean, U, Z, F, S, Q, W, aux1, aux2, aux3, red, status;
+  size_t total;
+};
+
+}  // namespace enkfmc
+
+struct enkfmc_plan {
+  // geometry and sizes
+  int32_t nx, ny, nvar, periodic_x, sdx, sdy, r_h, r_v, N;
+  std::vector<int32_t> nlev, var_off;
+  int64_t n = 0, m = 0;
+  int32_t ldu = 0;                 // row stride of the anomaly array (N rounded up to 16)
+  std::vector<int32_t> obs_idx;
+  // decomposition
+  std::vector<enkfmc::SubBox> subs;
+  std::vector<enkfmc::Block> blocks;
+  std::vector<int32_t> fit_glob, fit_blk;       // per fit row
+  std::vector<int64_t> row_ptr;                 // n_fit + 1, global CSR offsets
+  std::vector<int32_t> col;                     // block-local predecessor rows
+  std::vector<int64_t> csc_ptr;                 // n_fit + 1, transposed pattern
+  std::vector<int32_t> csc_row, csc_nz;         // block-local row i and entry (relative to nz0) of T_iq
+  std::vector<int32_t> interior_src;            // n: fit row that maps back onto each component
+  std::vector<int32_t> bobs_o, bobs_row;        // per block observation list
+  std::vector<int64_t> g2f_ptr;                 // n + 1: fit rows holding each component, sub-domain order
+  std::vector<int32_t> g2f;
+  std::vector<int64_t> o2b_ptr;                 // m + 1: block-observation entries of each observation
+  std::vector<int32_t> o2b;
+  int64_t n_fit = 0, nnz = 0, m_local = 0, sum_F = 0, sum_S = 0, sum_Q = 0;
+  int32_t max_p = 0, max_bn = 0, max_bm = 0;
+  enkfmc::Layout lay{};
+  // device state
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  int32_t device = -1;
+  int32_t fitted = 0, analyzed = 0;
+  double fit_ridge = 0.0;
+  const void *fit_xb = nullptr;
+  // optional per-phase timing with HIP events on the call's stream
+  int32_t timing = 0;
+  void *ev[64] = {};
+  uint64_t recorded = 0;
+  double phase_ms[32] = {};
+};
+
+namespace enkfmc {
+enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, const int32_t *obs_idx, int32_t m,
+                         std::string *err);
+void compute_layout(enkfmc_plan *p);
+}  // namespace enkfmc

@@ -1,0 +1,97 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared entry
+point, and its host planner reproduces the oracle's decomposition bit-exactly.
+No device call is made here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import geometry as G
+from paper_1606_00807_amd import EnkfmcError, Plan, _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    header = open(os.path.join(ROOT, "include", "enkfmc.h")).read()
+    names = sorted(set(re.findall(r"\b(enkfmc_[a-z_]+)\s*\(", header)))
+    assert "enkfmc_fit" in names and "enkfmc_analyze" in names and "enkfmc_analyze_backward" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.SIGNATURES)
+
+
+def _compare_patterns(geo, N, obs_idx, ks=None):
+    plan = Plan(geo, N, obs_idx)
+    ks = range(G.n_subdomains(geo)) if ks is None else ks
+    for k in ks:
+        ora = G.subdomain_pattern(geo, k, obs_idx)
+        got = plan.pattern(k)
+        assert np.array_equal(got["loc2glob"], ora.loc2glob), k
+        assert np.array_equal(got["interior"].astype(bool), ora.interior), k
+        assert np.array_equal(got["row_ptr"], ora.row_ptr), k
+        assert np.array_equal(got["col_idx"].astype(np.int64), ora.col_idx), k
+        assert np.array_equal(got["obs"].astype(np.int64), ora.obs), k
+        assert np.array_equal(got["obs_row"].astype(np.int64), ora.obs_row), k
+    return plan
+
+
+def test_pattern_ring():
+    p = synth.make_ring()
+    plan = _compare_patterns(p.geometry, p.N, p.obs_idx)
+    assert plan.info["nnz"] == 80 and plan.info["n_fit"] == 40
+
+
+@pytest.mark.parametrize("geo", [
+    synth.geometry(13, 11, [2, 1], True, 3, 2, 2, 1),
+    synth.geometry(12, 7, [1], False, 4, 3, 1, 0),
+    synth.geometry(10, 9, [3, 1], False, 3, 2, 2, 1),
+    synth.geometry(9, 5, [2], True, 1, 2, 2, 1),
+    synth.geometry(16, 8, [1, 3], True, 4, 2, 0, 0),
+])
+def test_pattern_small_geometries(geo):
+    n = synth.state_size(geo)
+    obs = synth.random_sites(n, n // 3, synth.rng(7, 2))
+    _compare_patterns(geo, 12, obs)
+
+
+def test_pattern_grid96x48():
+    p = synth.make_grid2d()
+    plan = _compare_patterns(p.geometry, p.N, p.obs_idx)
+    assert plan.info["n_fit"] == 9504 and plan.info["nnz"] == 184032
+
+
+def test_pattern_t63_sampled_subdomains():
+    geo = synth.geometry(192, 96, [7, 7, 7, 7, 1], True, 24, 12, 4, 1)
+    n = synth.state_size(geo)
+    obs = synth.random_sites(n, int(round(0.05 * n)), synth.rng(3, synth.STREAM_OBS_SITES))
+    # pole-row corner at the longitude seam, an interior tile, the other pole
+    plan = _compare_patterns(geo, 80, obs, ks=[0, 24 * 5 + 13, 24 * 11 + 23])
+    assert plan.info["n_subdomains"] == 288 and plan.info["n_fit"] == 2049024
+    assert plan.info["max_p"] == 121
+    assert plan.info["nnz"] == 161215104
+
+
+@pytest.mark.parametrize("case", ["unsorted", "duplicate", "range", "N", "wrap", "levels"])
+def test_plan_rejects_bad_input(case):
+    geo = synth.geometry(12, 8, [2], True, 3, 2, 1, 1)
+    obs = np.array([1, 5, 9], np.int32)
+    N = 10
+    if case == "unsorted":
+        obs = np.array([5, 1, 9], np.int32)
+    elif case == "duplicate":
+        obs = np.array([1, 5, 5], np.int32)
+    elif case == "range":
+        obs = np.array([1, 5, 12 * 8 * 2], np.int32)
+    elif case == "N":
+        N = 1
+    elif case == "wrap":
+        geo = synth.geometry(12, 8, [2], True, 3, 2, 5, 1)
+    elif case == "levels":
+        geo = synth.geometry(12, 8, [0], True, 3, 2, 1, 1)
+    with pytest.raises(EnkfmcError) as e:
+        Plan(geo, N, obs)
+    assert e.value.code == "EINVAL"
