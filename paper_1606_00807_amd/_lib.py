@@ -19,7 +19,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "ENONPOS_D", -4: "ENOCONV", 
 F32, F64 = 0, 1
 FIT_PLAIN, FIT_BATCHED = 0, 1
 SOLVE_DUAL = 0
-PHASES = ["anomaly", "fit", "dual_F", "dual_S", "dual_chol", "dual_Q", "dual_G", "sweep", "mapback", "backward"]
+PHASES = ["anomaly", "fit", "dual_F", "dual_S", "dual_chol", "dual_Q", "dual_G", "sweep", "mapback", "backward",
+          "tiles"]
 
 
 class Geometry(ctypes.Structure):

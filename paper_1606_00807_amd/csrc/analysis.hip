@@ -3,88 +3,201 @@
 // The local primal system of eq. (11) (per sub-domain, eq. 14 / Alg. 3),
 //   (T^T D^-1 T + H^T R^-1 H) Z = H^T R^-1 Delta,   Delta = Y^s - H X_b,
 // is solved exactly through the dual form of eqs. (12)-(13):
-//   B^ = T^-1 D T^-T,   F = T^-T H^T            (n_b x m_b, one backward sweep)
+//   B^ = T^-1 D T^-T,   F = T^-T H^T            (n_b x m_b, backward sweep)
 //   S  = R + H B^ H^T = R + F^T D F             (m_b x m_b, Cholesky)
 //   Q  = S^-1 Delta                             (m_b x N)
-//   Z  = B^ H^T Q = T^-1 (D (F Q))              (one forward sweep, N columns)
+//   Z  = B^ H^T Q = T^-1 (D (F Q))              (forward sweep, N columns)
 // Then X_a = X_b + Z on interior rows only (Alg. 2 merge; the interiors of
 // the sub-domains do not intersect, so every component is written once).
+//
+// Sweeps work on a block-sparse 16x16 tiling of T: rows are cut into 16-row
+// tiles (one latitude line of a 16-wide box); row tile R couples to the few
+// earlier column tiles holding its predecessors (dense tiles T_RC) and to
+// itself (unit lower triangular T_RR, inverted once after the fit).  A sweep
+// is then a sequence of v_mfma_f64_16x16x4 tile products per row tile.
+//
+// v_mfma_f64_16x16x4 conventions (lane l = 16q + c): A operand A[c][q],
+// B operand B[q][c], accumulator register r holds element (4r + q, c).
 #include "device.h"
 
 namespace enkfmc {
 
-// F = T^-T H^T: column o solves T^T f = e_{j_o} backwards (pull form over the
-// transposed pattern).  One lane per observation column; rows sequential.
-__global__ __launch_bounds__(64) void k_dual_F(const Block *__restrict__ blocks, const int64_t *__restrict__ csc_ptr,
-                                               const int32_t *__restrict__ csc_row,
-                                               const int32_t *__restrict__ csc_nz,
-                                               const int32_t *__restrict__ bobs_row,
-                                               const double *__restrict__ tval, double *__restrict__ F) {
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// Dense tiles T_RC (row-major) of row tile R, and the inverse of T_RR.
+// One 64-lane workgroup per (block, row tile).
+__global__ __launch_bounds__(64) void k_build_tiles(const Block *__restrict__ blocks,
+                                                    const int64_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col, const double *__restrict__ tval,
+                                                    const int64_t *__restrict__ rt_ptr,
+                                                    const int32_t *__restrict__ rt_col,
+                                                    const int32_t *__restrict__ rt_slot, double *__restrict__ tiles,
+                                                    double *__restrict__ tinv) {
+  extern __shared__ double sm[];
   const Block B = blocks[blockIdx.x];
-  const int o = blockIdx.y * 64 + threadIdx.x;
-  if (o >= B.m) return;
-  const int j = bobs_row[B.obs0 + o];
-  const int mb = B.m;
-  double *Fb = F + B.F0;
-  const double *tv = tval + B.nz0;
-  for (int q = B.n - 1; q >= 0; --q) {
-    double acc = (q == j) ? 1.0 : 0.0;
-    const int64_t c0 = csc_ptr[B.row0 + q], c1 = csc_ptr[B.row0 + q + 1];
-    for (int64_t t = c0; t < c1; ++t) acc -= tv[csc_nz[t]] * Fb[(int64_t)csc_row[t] * mb + o];
-    Fb[(int64_t)q * mb + o] = acc;
+  const int R = blockIdx.y;
+  if (R >= B.nrt) return;
+  const int lane = threadIdx.x;
+  const int64_t rt = B.rt0 + R;
+  const int64_t t0 = rt_ptr[rt];
+  const int nt = (int)(rt_ptr[rt + 1] - t0);
+  double *diag = sm + (size_t)nt * 256;
+  int *cols = (int *)(diag + 256);
+  int64_t *rp = (int64_t *)(cols + nt + 1 + ((nt + 1) & 1));
+  for (int e = lane; e < (nt + 1) * 256; e += 64) sm[e] = 0.0;
+  for (int t = lane; t < nt; t += 64) cols[t] = rt_col[t0 + t];
+  const int i0 = 16 * R, i1 = min(B.n, 16 * R + 16);
+  for (int i = lane; i <= i1 - i0; i += 64) rp[i] = row_ptr[B.row0 + i0 + i];
+  __syncthreads();
+  const int64_t k0 = rp[0], k1 = rp[i1 - i0];
+  for (int64_t k = k0 + lane; k < k1; k += 64) {
+    int i = 0;
+    while (rp[i + 1] <= k) ++i;
+    const int qcol = col[k];
+    const int C = qcol >> 4;
+    const int e = i * 16 + (qcol & 15);
+    if (C == R) {
+      diag[e] = tval[k];
+    } else {
+      int t = 0;
+      while (t < nt && cols[t] != C) ++t;
+      if (t < nt) sm[t * 256 + e] = tval[k];
+    }
+  }
+  __syncthreads();
+  for (int t = 0; t < nt; ++t) {
+    double *dst = tiles + (int64_t)rt_slot[t0 + t] * 256;
+    for (int e = lane; e < 256; e += 64) dst[e] = sm[t * 256 + e];
+  }
+  if (lane < 16) {
+    // column `lane` of (I + L)^-1 by forward substitution
+    const int j = lane;
+    double x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) v -= diag[i * 16 + k] * x[k];
+      x[i] = (i < j) ? 0.0 : v;
+    }
+    double *dst = tinv + rt * 256;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dst[i * 16 + j] = x[i];
   }
 }
 
-// S = R + F^T D F (lower triangle).
-__global__ __launch_bounds__(256) void k_dual_S(const Block *__restrict__ blocks, const int32_t *__restrict__ bobs_o,
-                                                const double *__restrict__ F, const double *__restrict__ dvec,
-                                                const double *__restrict__ r_diag, double *__restrict__ S) {
+// F = T^-T H^T, backward over row tiles; one wavefront per (block, 16 observation columns).
+__global__ __launch_bounds__(64) void k_bwd_sweep(const Block *__restrict__ blocks, const int64_t *__restrict__ ct_ptr,
+                                                  const int32_t *__restrict__ ct_row,
+                                                  const int32_t *__restrict__ ct_slot,
+                                                  const int32_t *__restrict__ bobs_row,
+                                                  const double *__restrict__ tiles, const double *__restrict__ tinv,
+                                                  double *__restrict__ F) {
   const Block B = blocks[blockIdx.x];
-  const int64_t idx = (int64_t)blockIdx.y * 256 + threadIdx.x;
-  const int mb = B.m;
-  if (idx >= (int64_t)mb * mb) return;
-  const int a = (int)(idx / mb), b = (int)(idx % mb);
-  if (b > a) return;
-  const double *Fb = F + B.F0;
-  const double *d = dvec + B.row0;
-  double s = 0.0;
-  for (int q = 0; q < B.n; ++q) s += (Fb[(int64_t)q * mb + a] * d[q]) * Fb[(int64_t)q * mb + b];
-  if (a == b) s += r_diag[bobs_o[B.obs0 + a]];
-  S[B.S0 + (int64_t)a * mb + b] = s;
+  const int oc = blockIdx.y;
+  if (16 * oc >= B.m) return;
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int o = 16 * oc + c;
+  const int jo = o < B.m ? bobs_row[B.obs0 + o] : -1;
+  const int ldf = B.ldf;
+  double *Fb = F + B.F0;
+  for (int C = B.nrt - 1; C >= 0; --C) {
+    d4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = (16 * C + 4 * r + q == jo) ? 1.0 : 0.0;
+    const int64_t s0 = ct_ptr[B.rt0 + C], s1 = ct_ptr[B.rt0 + C + 1];
+    for (int64_t t = s0; t < s1; ++t) {
+      const int R = ct_row[t];
+      const double *Tt = tiles + (int64_t)ct_slot[t] * 256;
+      const double *Fr = Fb + (int64_t)(16 * R) * ldf + 16 * oc + c;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc)
+        acc = mfma64(-Tt[(4 * kc + q) * 16 + c], Fr[(int64_t)(4 * kc + q) * ldf], acc);
+    }
+    const double *Ti = tinv + (B.rt0 + C) * 256;
+    d4 out = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) out = mfma64(Ti[(4 * kc + q) * 16 + c], acc[kc], out);
+    double *Fc = Fb + (int64_t)(16 * C) * ldf + 16 * oc + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Fc[(int64_t)(4 * r + q) * ldf] = out[r];
+  }
 }
 
-// In-place Cholesky of each block's S (lower triangle), one workgroup per block.
+// S = R + F^T D F (lower tiles, stride ldf); one wavefront per (block, tile column J).
+__global__ __launch_bounds__(64) void k_dual_S(const Block *__restrict__ blocks, const int32_t *__restrict__ bobs_o,
+                                               const double *__restrict__ F, const double *__restrict__ dvec,
+                                               const double *__restrict__ r_diag, double *__restrict__ S) {
+  constexpr int kMaxTiles = 8;
+  const Block B = blocks[blockIdx.x];
+  const int J = blockIdx.y;
+  const int TJ = B.ldf >> 4;
+  if (J >= TJ) return;
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int ldf = B.ldf;
+  const double *Fb = F + B.F0;
+  d4 acc[kMaxTiles];
+#pragma unroll
+  for (int I = 0; I < kMaxTiles; ++I) acc[I] = d4{0.0, 0.0, 0.0, 0.0};
+  const int ksteps = 4 * B.nrt;
+  for (int ks = 0; ks < ksteps; ++ks) {
+    const int k = 4 * ks + q;
+    const double dk = k < B.n ? dvec[B.row0 + k] : 0.0;
+    const double *Fk = Fb + (int64_t)k * ldf + c;
+    const double b = dk * Fk[16 * J];
+#pragma unroll
+    for (int I = 0; I < kMaxTiles; ++I)
+      if (I >= J && I < TJ) acc[I] = mfma64(Fk[16 * I], b, acc[I]);
+  }
+  double *Sb = S + B.S0;
+#pragma unroll
+  for (int I = 0; I < kMaxTiles; ++I) {
+    if (I >= J && I < TJ) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * I + 4 * r + q, bb = 16 * J + c;
+        double v = acc[I][r];
+        if (a == bb) v = a < B.m ? v + r_diag[bobs_o[B.obs0 + a]] : 1.0;
+        Sb[(int64_t)a * ldf + bb] = v;
+      }
+    }
+  }
+}
+
+// In-place Cholesky of each block's S (m x m lower part, stride ldf), one workgroup per block.
 __global__ __launch_bounds__(256) void k_dual_chol(const Block *__restrict__ blocks, double *__restrict__ S,
                                                    int32_t *status) {
   __shared__ int bad;
   const Block B = blocks[blockIdx.x];
-  const int m = B.m, tid = threadIdx.x;
+  const int m = B.m, ld = B.ldf, tid = threadIdx.x;
   double *L = S + B.S0;
   if (tid == 0) bad = 0;
   for (int k = 0; k < m; ++k) {
     __syncthreads();
     if (tid == 0) {
-      const double piv = L[(int64_t)k * m + k];
+      const double piv = L[(int64_t)k * ld + k];
       if (!(piv > 0.0)) bad = 1;
-      else L[(int64_t)k * m + k] = sqrt(piv);
+      else L[(int64_t)k * ld + k] = sqrt(piv);
     }
     __syncthreads();
     if (bad) {
       if (tid == 0) set_error(status, ENKFMC_ENOTSPD, -1 - (int32_t)blockIdx.x);
       return;
     }
-    const double lkk = L[(int64_t)k * m + k];
-    for (int i = k + 1 + tid; i < m; i += 256) L[(int64_t)i * m + k] /= lkk;
+    const double lkk = L[(int64_t)k * ld + k];
+    for (int i = k + 1 + tid; i < m; i += 256) L[(int64_t)i * ld + k] /= lkk;
     __syncthreads();
     const int t = m - k - 1;
     for (int64_t idx = tid; idx < (int64_t)t * t; idx += 256) {
       const int i = k + 1 + (int)(idx / t), j = k + 1 + (int)(idx % t);
-      if (j <= i) L[(int64_t)i * m + j] -= L[(int64_t)i * m + k] * L[(int64_t)j * m + k];
+      if (j <= i) L[(int64_t)i * ld + j] -= L[(int64_t)i * ld + k] * L[(int64_t)j * ld + k];
     }
   }
 }
 
-// Q = S^-1 Delta, one lane per member column.
+// Q = S^-1 Delta, one lane per member column; rows m..ldf-1 of Q are zeroed.
 template <typename TX>
 __global__ __launch_bounds__(64) void k_dual_Q(const Block *__restrict__ blocks, const int32_t *__restrict__ bobs_o,
                                                const int32_t *__restrict__ bobs_row,
@@ -93,53 +206,76 @@ __global__ __launch_bounds__(64) void k_dual_Q(const Block *__restrict__ blocks,
                                                int N, double *__restrict__ Q) {
   const Block B = blocks[blockIdx.x];
   const int c = blockIdx.y * 64 + threadIdx.x;
-  if (c >= N) return;
-  const int m = B.m;
+  if (c >= N || B.m == 0) return;
+  const int m = B.m, lds = B.ldf;
   const double *L = S + B.S0;
   double *q = Q + B.Q0;
   for (int a = 0; a < m; ++a) {
     const int o = bobs_o[B.obs0 + a];
     const int64_t g = fit_glob[B.row0 + bobs_row[B.obs0 + a]];
     double acc = Y[(int64_t)o * N + c] - (double)Xb[g * ld + c];
-    for (int b = 0; b < a; ++b) acc -= L[(int64_t)a * m + b] * q[(int64_t)b * N + c];
-    q[(int64_t)a * N + c] = acc / L[(int64_t)a * m + a];
+    for (int b = 0; b < a; ++b) acc -= L[(int64_t)a * lds + b] * q[(int64_t)b * N + c];
+    q[(int64_t)a * N + c] = acc / L[(int64_t)a * lds + a];
   }
   for (int a = m - 1; a >= 0; --a) {
     double acc = q[(int64_t)a * N + c];
-    for (int b = a + 1; b < m; ++b) acc -= L[(int64_t)b * m + a] * q[(int64_t)b * N + c];
-    q[(int64_t)a * N + c] = acc / L[(int64_t)a * m + a];
+    for (int b = a + 1; b < m; ++b) acc -= L[(int64_t)b * lds + a] * q[(int64_t)b * N + c];
+    q[(int64_t)a * N + c] = acc / L[(int64_t)a * lds + a];
   }
+  for (int a = m; a < lds; ++a) q[(int64_t)a * N + c] = 0.0;
 }
 
-// Z rows = D (F Q)   (right-hand side of the final forward sweep).
-__global__ __launch_bounds__(256) void k_dual_G(const Block *__restrict__ blocks, const double *__restrict__ F,
-                                                const double *__restrict__ Q, const double *__restrict__ dvec, int N,
-                                                double *__restrict__ Z) {
+// Z = T^-1 (D (F Q)), forward over row tiles; one wavefront per (block, 16 member columns).
+__global__ __launch_bounds__(64) void k_fwd_sweep(const Block *__restrict__ blocks, const int64_t *__restrict__ rt_ptr,
+                                                  const int32_t *__restrict__ rt_col,
+                                                  const int32_t *__restrict__ rt_slot,
+                                                  const double *__restrict__ tiles, const double *__restrict__ tinv,
+                                                  const double *__restrict__ F, const double *__restrict__ Q,
+                                                  const double *__restrict__ dvec, int N, double *__restrict__ Z) {
   const Block B = blocks[blockIdx.x];
-  const int64_t idx = (int64_t)blockIdx.y * 256 + threadIdx.x;
-  if (idx >= (int64_t)B.n * N) return;
-  const int q = (int)(idx / N), c = (int)(idx % N);
-  const int mb = B.m;
-  const double *Fr = F + B.F0 + (int64_t)q * mb;
+  const int cc = blockIdx.y;
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int colj = 16 * cc + c;
+  const bool colok = colj < N;
+  const int coll = colok ? colj : 0;
+  const int ldf = B.ldf;
+  const double *Fb = F + B.F0;
   const double *Qb = Q + B.Q0;
-  double s = 0.0;
-  for (int a = 0; a < mb; ++a) s += Fr[a] * Qb[(int64_t)a * N + c];
-  Z[(B.row0 + q) * N + c] = dvec[B.row0 + q] * s;
-}
-
-// Z = T^-1 Z in place (forward sweep), one lane per member column.
-__global__ __launch_bounds__(64) void k_fwd_sweep(const Block *__restrict__ blocks, const int64_t *__restrict__ row_ptr,
-                                                  const int32_t *__restrict__ col, const double *__restrict__ tval,
-                                                  int N, double *__restrict__ Z) {
-  const Block B = blocks[blockIdx.x];
-  const int c = blockIdx.y * 64 + threadIdx.x;
-  if (c >= N) return;
   double *Zb = Z + B.row0 * N;
-  for (int i = 0; i < B.n; ++i) {
-    double acc = Zb[(int64_t)i * N + c];
-    const int64_t k0 = row_ptr[B.row0 + i], k1 = row_ptr[B.row0 + i + 1];
-    for (int64_t k = k0; k < k1; ++k) acc -= tval[k] * Zb[(int64_t)col[k] * N + c];
-    Zb[(int64_t)i * N + c] = acc;
+  for (int R = 0; R < B.nrt; ++R) {
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    const double *Fr = Fb + (int64_t)(16 * R + c) * ldf + q;
+    for (int ks = 0; ks < (ldf >> 2); ++ks) {
+      const double bq = Qb[(int64_t)(4 * ks + q) * N + coll];
+      acc = mfma64(Fr[4 * ks], colok ? bq : 0.0, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * R + 4 * r + q;
+      acc[r] *= row < B.n ? dvec[B.row0 + row] : 0.0;
+    }
+    const int64_t s0 = rt_ptr[B.rt0 + R], s1 = rt_ptr[B.rt0 + R + 1];
+    for (int64_t t = s0; t < s1; ++t) {
+      const int C = rt_col[t];
+      const double *Tt = tiles + (int64_t)rt_slot[t] * 256 + c * 16 + q;
+      const double *Zc = Zb + (int64_t)(16 * C + q) * N + coll;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        const double z = Zc[(int64_t)(4 * kc) * N];
+        acc = mfma64(-Tt[4 * kc], colok ? z : 0.0, acc);
+      }
+    }
+    const double *Ti = tinv + (B.rt0 + R) * 256 + c * 16 + q;
+    d4 out = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) out = mfma64(Ti[4 * kc], acc[kc], out);
+    if (colok) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * R + 4 * r + q;
+        if (row < B.n) Zb[(int64_t)row * N + colj] = out[r];
+      }
+    }
   }
 }
 
@@ -155,20 +291,42 @@ __global__ __launch_bounds__(256) void k_mapback(const TX *__restrict__ Xb, int6
   Xa[idx] = (TO)((double)Xb[g * ld + c] + Z[(int64_t)src[g] * N + c]);
 }
 
+size_t build_tiles_lds(const enkfmc_plan *p) {
+  const int nt = p->max_rt_tiles;
+  return (size_t)(nt + 1) * 256 * 8 + (size_t)(nt + 2) * 4 + 17 * 8 + 16;
+}
+
+int max_block_tiles(const enkfmc_plan *p) {
+  int mx = 0;
+  for (const Block &B : p->blocks) mx = B.nrt > mx ? B.nrt : mx;
+  return mx;
+}
+
+hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s) {
+  const size_t lds = build_tiles_lds(p);
+  hipError_t e = hipFuncSetAttribute((const void *)k_build_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  phase_begin(p, ENKFMC_PH_TILES, s);
+  hipLaunchKernelGGL(k_build_tiles, dim3((unsigned)p->blocks.size(), (unsigned)max_block_tiles(p)), dim3(64), lds, s,
+                     d.blocks, d.row_ptr, d.col, d.tval, d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tinv);
+  phase_end(p, ENKFMC_PH_TILES, s);
+  return hipGetLastError();
+}
+
 template <typename TX>
 static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int64_t ld, const double *Y,
                                  const double *r_diag, void *Xa, int32_t out_dtype, hipStream_t s) {
   const unsigned nb = (unsigned)p->blocks.size();
   const int N = p->N;
+  const unsigned oc = (unsigned)((p->max_bm + 15) / 16);
+  if (oc > 8) return hipErrorInvalidValue;   // k_dual_S keeps at most 8 tile rows
   if (p->max_bm > 0) {
     phase_begin(p, ENKFMC_PH_DUAL_F, s);
-    hipLaunchKernelGGL(k_dual_F, dim3(nb, (p->max_bm + 63) / 64), dim3(64), 0, s, d.blocks, d.csc_ptr, d.csc_row,
-                       d.csc_nz, d.bobs_row, d.tval, d.F);
+    hipLaunchKernelGGL(k_bwd_sweep, dim3(nb, oc), dim3(64), 0, s, d.blocks, d.ct_ptr, d.ct_row, d.ct_slot, d.bobs_row,
+                       d.tiles, d.tinv, d.F);
     phase_end(p, ENKFMC_PH_DUAL_F, s);
-    const int64_t sq = (int64_t)p->max_bm * p->max_bm;
     phase_begin(p, ENKFMC_PH_DUAL_S, s);
-    hipLaunchKernelGGL(k_dual_S, dim3(nb, (unsigned)((sq + 255) / 256)), dim3(256), 0, s, d.blocks, d.bobs_o, d.F,
-                       d.dvec, r_diag, d.S);
+    hipLaunchKernelGGL(k_dual_S, dim3(nb, oc), dim3(64), 0, s, d.blocks, d.bobs_o, d.F, d.dvec, r_diag, d.S);
     phase_end(p, ENKFMC_PH_DUAL_S, s);
     phase_begin(p, ENKFMC_PH_DUAL_CHOL, s);
     hipLaunchKernelGGL(k_dual_chol, dim3(nb), dim3(256), 0, s, d.blocks, d.S, d.status);
@@ -178,14 +336,10 @@ static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
                        d.fit_glob, d.S, Y, Xb, ld, N, d.Q);
     phase_end(p, ENKFMC_PH_DUAL_Q, s);
   }
-  const int64_t nbN = (int64_t)p->max_bn * N;
-  phase_begin(p, ENKFMC_PH_DUAL_G, s);
-    hipLaunchKernelGGL(k_dual_G, dim3(nb, (unsigned)((nbN + 255) / 256)), dim3(256), 0, s, d.blocks, d.F, d.Q, d.dvec, N,
-                     d.Z);
-    phase_end(p, ENKFMC_PH_DUAL_G, s);
   phase_begin(p, ENKFMC_PH_SWEEP, s);
-    hipLaunchKernelGGL(k_fwd_sweep, dim3(nb, (N + 63) / 64), dim3(64), 0, s, d.blocks, d.row_ptr, d.col, d.tval, N, d.Z);
-    phase_end(p, ENKFMC_PH_SWEEP, s);
+  hipLaunchKernelGGL(k_fwd_sweep, dim3(nb, (N + 15) / 16), dim3(64), 0, s, d.blocks, d.rt_ptr, d.rt_col, d.rt_slot,
+                     d.tiles, d.tinv, d.F, d.Q, d.dvec, N, d.Z);
+  phase_end(p, ENKFMC_PH_SWEEP, s);
   const int64_t tot = p->n * N;
   const dim3 g((unsigned)((tot + 255) / 256));
   phase_begin(p, ENKFMC_PH_MAPBACK, s);

@@ -136,6 +136,12 @@ enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes,
   HIPCHK(put(p, L.g2f, p->g2f, s), "set_workspace");
   HIPCHK(put(p, L.o2b_ptr, p->o2b_ptr, s), "set_workspace");
   HIPCHK(put(p, L.o2b, p->o2b, s), "set_workspace");
+  HIPCHK(put(p, L.rt_ptr, p->rt_ptr, s), "set_workspace");
+  HIPCHK(put(p, L.rt_col, p->rt_col, s), "set_workspace");
+  HIPCHK(put(p, L.rt_slot, p->rt_slot, s), "set_workspace");
+  HIPCHK(put(p, L.ct_ptr, p->ct_ptr, s), "set_workspace");
+  HIPCHK(put(p, L.ct_row, p->ct_row, s), "set_workspace");
+  HIPCHK(put(p, L.ct_slot, p->ct_slot, s), "set_workspace");
   HIPCHK(hipStreamSynchronize(s), "set_workspace");
   return ENKFMC_OK;
 }
@@ -160,6 +166,7 @@ enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t 
   } else {
     HIPCHK(launch_fit_batched(p, d, ridge, s), "fit: batched launch");
   }
+  HIPCHK(launch_build_tiles(p, d, s), "fit: tile launch");
   st = finish(p, s, "fit");
   if (st != ENKFMC_OK) return st;
   p->fitted = 1;
@@ -175,6 +182,8 @@ enkfmc_status enkfmc_analyze(enkfmc_plan *p, const void *Xb, int32_t dtype, int6
   if (out_dtype != ENKFMC_F32 && out_dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "analyze: bad out_dtype");
   if (ld < p->N) return fail(ENKFMC_EINVAL, "analyze: ld < N");
   if (solver != ENKFMC_SOLVE_DUAL) return fail(ENKFMC_EINVAL, "analyze: unknown solver");
+  if (p->max_bm > 128)
+    return fail(ENKFMC_EUNSUPPORTED, "analyze: a block holds more than 128 observations (dual-form tile limit)");
   if (!p->fitted || p->fit_xb != Xb) return fail(ENKFMC_ESTATE, "analyze: needs the preceding fit on the same X_b");
   hipStream_t s = (hipStream_t)stream;
   enkfmc_status st = begin(p, s, "analyze");

@@ -19,6 +19,9 @@ struct Dev {
   const int32_t *g2f;
   const int64_t *o2b_ptr;
   const int32_t *o2b;
+  const int64_t *rt_ptr, *ct_ptr;
+  const int32_t *rt_col, *rt_slot, *ct_row, *ct_slot;
+  double *tiles, *tinv;
   double *tval, *dvec, *mean, *U, *Z, *F, *S, *Q, *W, *aux1, *aux2, *aux3, *red;
   int32_t *status;
 };
@@ -42,6 +45,14 @@ inline Dev make_dev(enkfmc_plan *p) {
   d.g2f = (const int32_t *)(w + L.g2f);
   d.o2b_ptr = (const int64_t *)(w + L.o2b_ptr);
   d.o2b = (const int32_t *)(w + L.o2b);
+  d.rt_ptr = (const int64_t *)(w + L.rt_ptr);
+  d.rt_col = (const int32_t *)(w + L.rt_col);
+  d.rt_slot = (const int32_t *)(w + L.rt_slot);
+  d.ct_ptr = (const int64_t *)(w + L.ct_ptr);
+  d.ct_row = (const int32_t *)(w + L.ct_row);
+  d.ct_slot = (const int32_t *)(w + L.ct_slot);
+  d.tiles = (double *)(w + L.tiles);
+  d.tinv = (double *)(w + L.tinv);
   d.tval = (double *)(w + L.tval);
   d.dvec = (double *)(w + L.dvec);
   d.mean = (double *)(w + L.mean);
@@ -97,6 +108,7 @@ inline void phase_end(enkfmc_plan *p, int ph, hipStream_t s) {
 hipError_t launch_anomaly(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, hipStream_t s);
 hipError_t launch_fit_plain(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
 hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
+hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s);
 hipError_t launch_analysis_dual(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld,
                                 const double *Y, const double *r_diag, void *Xa, int32_t out_dtype, hipStream_t s);
 hipError_t launch_backward(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, const double *Y,

@@ -155,8 +155,10 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
     Block &B = p->blocks[b];
     B.obs0 = (int64_t)p->bobs_o.size();
     B.m = (int32_t)bo[b].size();
+    B.nrt = (B.n + 15) / 16;
+    B.ldf = (B.m + 15) / 16 * 16;
     B.F0 = sumF; B.S0 = sumS; B.Q0 = sumQ;
-    sumF += (int64_t)B.n * B.m; sumS += (int64_t)B.m * B.m; sumQ += (int64_t)B.m * N;
+    sumF += (int64_t)16 * B.nrt * B.ldf; sumS += (int64_t)B.ldf * B.ldf; sumQ += (int64_t)B.ldf * N;
     p->max_bm = std::max(p->max_bm, B.m);
     for (size_t t = 0; t < bo[b].size(); ++t) {
       p->bobs_o.push_back(bo[b][t]);
@@ -201,6 +203,45 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
           p->csc_nz[slot] = (int32_t)(k - B.nz0);
         }
   }
+  // block-sparse tiling of each block's T (16-row tiles)
+  p->rt_ptr.assign(1, 0);
+  p->rt_col.clear(); p->rt_slot.clear();
+  p->n_rt = 0; p->n_slots = 0; p->max_rt_tiles = 0;
+  for (Block &B : p->blocks) {
+    B.rt0 = p->n_rt;
+    for (int32_t R = 0; R < B.nrt; ++R) {
+      std::vector<int32_t> cs;
+      const int32_t i1 = std::min(B.n, 16 * R + 16);
+      for (int32_t i = 16 * R; i < i1; ++i)
+        for (int64_t k = p->row_ptr[B.row0 + i]; k < p->row_ptr[B.row0 + i + 1]; ++k)
+          if (p->col[k] / 16 != R) cs.push_back(p->col[k] / 16);
+      std::sort(cs.begin(), cs.end());
+      cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+      for (int32_t c : cs) { p->rt_col.push_back(c); p->rt_slot.push_back((int32_t)p->n_slots++); }
+      p->rt_ptr.push_back((int64_t)p->rt_col.size());
+      p->max_rt_tiles = std::max(p->max_rt_tiles, (int32_t)cs.size());
+      ++p->n_rt;
+    }
+  }
+  if (p->n_slots >= (int64_t(1) << 31)) { *err = "too many tiles"; return ENKFMC_EUNSUPPORTED; }
+  // transposed tile lists: for every column tile, the later row tiles (ascending)
+  p->ct_ptr.assign(p->n_rt + 1, 0);
+  for (const Block &B : p->blocks)
+    for (int32_t R = 0; R < B.nrt; ++R)
+      for (int64_t t = p->rt_ptr[B.rt0 + R]; t < p->rt_ptr[B.rt0 + R + 1]; ++t) p->ct_ptr[B.rt0 + p->rt_col[t] + 1]++;
+  for (int64_t t = 0; t < p->n_rt; ++t) p->ct_ptr[t + 1] += p->ct_ptr[t];
+  p->ct_row.assign(p->rt_col.size(), 0);
+  p->ct_slot.assign(p->rt_col.size(), 0);
+  {
+    std::vector<int64_t> fill(p->ct_ptr.begin(), p->ct_ptr.end() - 1);
+    for (const Block &B : p->blocks)
+      for (int32_t R = 0; R < B.nrt; ++R)
+        for (int64_t t = p->rt_ptr[B.rt0 + R]; t < p->rt_ptr[B.rt0 + R + 1]; ++t) {
+          const int64_t slot = fill[B.rt0 + p->rt_col[t]]++;
+          p->ct_row[slot] = R;
+          p->ct_slot[slot] = p->rt_slot[t];
+        }
+  }
   compute_layout(p);
   return ENKFMC_OK;
 }
@@ -226,6 +267,12 @@ void compute_layout(enkfmc_plan *p) {
   L.g2f = take(nf * 4);
   L.o2b_ptr = take((m + 1) * 8);
   L.o2b = take(ml * 4);
+  L.rt_ptr = take((size_t)(p->n_rt + 1) * 8);
+  L.rt_col = take(p->rt_col.size() * 4);
+  L.rt_slot = take(p->rt_slot.size() * 4);
+  L.ct_ptr = take((size_t)(p->n_rt + 1) * 8);
+  L.ct_row = take(p->ct_row.size() * 4);
+  L.ct_slot = take(p->ct_slot.size() * 4);
   L.tval = take(nz * 8);
   L.dvec = take(nf * 8);
   L.mean = take(n * 8);
@@ -239,6 +286,8 @@ void compute_layout(enkfmc_plan *p) {
   L.aux2 = take(nf * N * 8);
   L.aux3 = take(nz * 8);
   L.red = take(nf * 8 + 64);
+  L.tiles = take((size_t)p->n_slots * 256 * 8);
+  L.tinv = take((size_t)p->n_rt * 256 * 8);
   L.status = take(64);
   L.total = off;
 }

@@ -21,9 +21,12 @@ struct Block {
   int64_t row0;          // first fit row (global fit numbering)
   int64_t nz0;           // first CSR entry of the block
   int64_t obs0;          // first entry of the block's observation list
-  int64_t F0;            // offset of the block's F = T^-T H^T (n x m, row-major)
-  int64_t S0;            // offset of the block's m x m innovation matrix
-  int64_t Q0;            // offset of the block's m x N solve
+  int64_t F0;            // offset of the block's F = T^-T H^T (16*nrt x ldf, row-major)
+  int64_t S0;            // offset of the block's ldf x ldf innovation matrix
+  int64_t Q0;            // offset of the block's ldf x N solve
+  int32_t nrt;           // 16-row tiles of the block (the last one may be partial)
+  int32_t ldf;           // observation count rounded up to 16
+  int64_t rt0;           // first row tile (global row-tile numbering)
 };
 
 struct SubBox {
@@ -36,7 +39,8 @@ struct SubBox {
 struct Layout {
   size_t blocks, fit_glob, fit_blk, row_ptr, col, csc_ptr, csc_row, csc_nz, interior_src, bobs_o, bobs_row;
   size_t g2f_ptr, g2f, o2b_ptr, o2b;
-  size_t tval, dvec, mean, U, Z, F, S, Q, W, aux1, aux2, aux3, red, status;
+  size_t rt_ptr, rt_col, rt_slot, ct_ptr, ct_row, ct_slot;
+  size_t tval, dvec, mean, U, Z, F, S, Q, W, aux1, aux2, aux3, red, tiles, tinv, status;
   size_t total;
 };
 
@@ -63,6 +67,13 @@ struct enkfmc_plan {
   std::vector<int32_t> g2f;
   std::vector<int64_t> o2b_ptr;                 // m + 1: block-observation entries of each observation
   std::vector<int32_t> o2b;
+  // block-sparse 16x16 tiling of T: per row tile the strictly-earlier column
+  // tiles holding entries (ascending), per column tile the later row tiles
+  std::vector<int64_t> rt_ptr, ct_ptr;          // n_rt + 1
+  std::vector<int32_t> rt_col, ct_row;          // tile indices inside the block
+  std::vector<int32_t> rt_slot, ct_slot;        // dense tile slot
+  int64_t n_rt = 0, n_slots = 0;
+  int32_t max_rt_tiles = 0;
   int64_t n_fit = 0, nnz = 0, m_local = 0, sum_F = 0, sum_S = 0, sum_Q = 0;
   int32_t max_p = 0, max_bn = 0, max_bm = 0;
   enkfmc::Layout lay{};
