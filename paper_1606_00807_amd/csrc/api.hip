@@ -124,6 +124,7 @@ enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes,
          "set_workspace");
   HIPCHK(put(p, L.fit_glob, p->fit_glob, s), "set_workspace");
   HIPCHK(put(p, L.fit_blk, p->fit_blk, s), "set_workspace");
+  HIPCHK(put(p, L.fit_rows, p->fit_rows, s), "set_workspace");
   HIPCHK(put(p, L.row_ptr, p->row_ptr, s), "set_workspace");
   HIPCHK(put(p, L.col, p->col, s), "set_workspace");
   HIPCHK(put(p, L.csc_ptr, p->csc_ptr, s), "set_workspace");

@@ -9,7 +9,7 @@ namespace enkfmc {
 
 struct Dev {
   const Block *blocks;
-  const int32_t *fit_glob, *fit_blk;
+  const int32_t *fit_glob, *fit_blk, *fit_rows;
   const int64_t *row_ptr;
   const int32_t *col;
   const int64_t *csc_ptr;
@@ -33,6 +33,7 @@ inline Dev make_dev(enkfmc_plan *p) {
   d.blocks = (const Block *)(w + L.blocks);
   d.fit_glob = (const int32_t *)(w + L.fit_glob);
   d.fit_blk = (const int32_t *)(w + L.fit_blk);
+  d.fit_rows = (const int32_t *)(w + L.fit_rows);
   d.row_ptr = (const int64_t *)(w + L.row_ptr);
   d.col = (const int32_t *)(w + L.col);
   d.csc_ptr = (const int64_t *)(w + L.csc_ptr);
@@ -96,11 +97,11 @@ template <typename T> __device__ inline double ld_as_double(const T *p) { return
 // Phase timing: records a HIP event pair around a kernel when the plan asks for it.
 inline void phase_begin(enkfmc_plan *p, int ph, hipStream_t s) {
   if (!p->timing) return;
-  hipEventRecord((hipEvent_t)p->ev[2 * ph], s);
+  (void)hipEventRecord((hipEvent_t)p->ev[2 * ph], s);
 }
 inline void phase_end(enkfmc_plan *p, int ph, hipStream_t s) {
   if (!p->timing) return;
-  hipEventRecord((hipEvent_t)p->ev[2 * ph + 1], s);
+  (void)hipEventRecord((hipEvent_t)p->ev[2 * ph + 1], s);
   p->recorded |= (uint64_t(1) << ph);
 }
 

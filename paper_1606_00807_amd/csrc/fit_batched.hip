@@ -7,17 +7,20 @@
 //      p predecessors) or X = U_P^T (p-form, reduction over the N members),
 //      accumulated by v_mfma_f64_16x16x4 into the T(T+1)/2 lower 16x16 tiles.
 //      Rows/columns m..16T-1 are padded with the identity.
-//   2. An extra tile row holds the right-hand side v^T (v = u or U_P u), so
-//      the Cholesky factorisation of the bordered matrix [[G, v], [v^T, .]]
-//      yields y = L^-1 v in its last row (forward substitution for free).
+//   2. The right-hand side v (v = u, or U_P u accumulated in the same pass) is
+//      a bordering row, so factoring [[G, v], [v^T, .]] also yields
+//      y = L^-1 v (forward substitution for free).
 //   3. Blocked right-looking Cholesky, panel width 16: inside a panel the 16
 //      columns are eliminated one at a time (column broadcast through a
 //      wavefront-private LDS buffer); the trailing tiles are then updated with
-//      v_mfma_f64_16x16x4 (A and B operands transposed through LDS).
+//      v_mfma_f64_16x16x4 (operands transposed through LDS).
 //   4. Back substitution L^T x = y, blocked: off-diagonal tiles by
 //      wavefront reductions, diagonal tiles by 16 scalar steps.
 //   5. p-form: beta = x, eps = u - U_P^T beta;
 //      kernel form: w = x, beta = U_P w, eps = mu w.   d = eps^T eps/(N-1).
+//
+// Every (T, form) pair is its own kernel, launched over a precomputed bucket
+// of rows, so that each kernel carries only the registers its T needs.
 //
 // Layout of a v_mfma_f64_16x16x4 accumulator (lane l = 16q + c, register r):
 // element (4r + q, c).  A operand: lane l holds A[c][q]; B operand: B[q][c].
@@ -31,11 +34,13 @@ constexpr int kMaxT = 5;          // largest tile count handled here (m <= 80)
 constexpr int kMaxP = 128;        // largest predecessor count handled here
 constexpr int kTileLd = 17;       // padded row stride of the transpose buffer
 
+template <int T>
 struct WaveLds {                  // wavefront-private LDS (doubles unless noted)
-  int pidx[kMaxP];
-  double col[16 * (kMaxT + 1)];
-  double vec[16 * (kMaxT + 1)];
-  double tile[(kMaxT + 1) * 16 * kTileLd];
+  int pidx[kMaxP + 8];            // global rows of the predecessors, pad row beyond p
+  double col[16 * (T + 1)];
+  double vec[16 * (T + 1)];
+  double dinv[16 * T];            // 1 / L_kk of the factor
+  double tile[T * 16 * kTileLd];
 };
 
 __device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
@@ -47,57 +52,106 @@ __device__ inline double readlane_d(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Orders this wavefront's LDS accesses (LDS executes a wavefront's operations
-// in issue order; this keeps the compiler from moving them).
+// Orders this wavefront's LDS accesses (lanes exchange values through LDS):
+// waits for the wavefront's outstanding LDS operations and keeps the
+// compiler from moving memory operations or other code across this point.
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps
+// (quadratic convergence from the estimate's ~22 bits to full precision).
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double r = fma(-h * y, y, 0.5);
+  y = fma(y, r, y);
+  r = fma(-h * y, y, 0.5);
+  y = fma(y, r, y);
+  return y;
 }
 
 template <int T>
-__device__ __forceinline__ constexpr int tix(int I, int J) {  // lower tile (I >= J, I < T); aug row I == T
-  return I < T ? I * (I + 1) / 2 + J : T * (T + 1) / 2 + J;
-}
+__device__ __forceinline__ constexpr int tix(int I, int J) { return I * (I + 1) / 2 + J; }
 
-template <int T>
-__device__ __forceinline__ void fit_row(const int lane, const int64_t r, const int p, const int N, const bool kform, const double mu,
-                        const double *__restrict__ U, const int ldu, const double *__restrict__ u, WaveLds &L,
-                        double *__restrict__ tval, const int64_t lo, double *__restrict__ dvec, int32_t *status) {
+template <int T, bool KF>
+__device__ __forceinline__ void fit_row(const int lane, const int64_t r, const int p, const int N, const double mu,
+                                        const double *__restrict__ U, const int ldu, const int uoff, WaveLds<T> &L,
+                                        double *__restrict__ tval, const int64_t lo, double *__restrict__ dvec,
+                                        int32_t *status) {
   constexpr int NT = T * (T + 1) / 2;
   const int q = lane >> 4, c = lane & 15;
-  const int m = kform ? N : p;
-  d4 acc[NT + T];
+  const int m = KF ? N : p;
+  d4 acc[NT];
 #pragma unroll
-  for (int t = 0; t < NT + T; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  double augv[T];   // bordering row: element 16J + c at lane (q = 0, c)
 
-  // ---- 1. Gram -------------------------------------------------------------
-  const int K = kform ? p : N;
-  const int ksteps = (K + 3) >> 2;
-  for (int ks = 0; ks < ksteps; ++ks) {
-    double f[T];
-    if (kform) {
-      const int k = 4 * ks + q;
-      const int kk = k < p ? k : p - 1;
-      const double *src = U + (int64_t)L.pidx[kk] * ldu;
+  // ---- 1. Gram (+ right-hand side) -----------------------------------------
+  // pidx[k] for k >= p names the all-zero pad row of U, so padded fragments
+  // load zeros; the loads of step ks+1 are issued before the MFMAs of ks.
+  if (KF) {
+    const int ksteps = (p + 3) >> 2;
+    double fa[T], fb[T];
+    {
+      const int off = L.pidx[q] * ldu + c;
+#pragma unroll
+      for (int I = 0; I < T; ++I) fa[I] = U[off + 16 * I];
+    }
+    for (int ks = 0; ks < ksteps; ks += 2) {
+      const int offb = L.pidx[4 * ks + 4 + q] * ldu + c;
+#pragma unroll
+      for (int I = 0; I < T; ++I) fb[I] = U[offb + 16 * I];
+#pragma unroll
+      for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[I], fa[J], acc[tix<T>(I, J)]);
+      if (ks + 1 >= ksteps) break;
+      const int offa = L.pidx[4 * ks + 8 + q] * ldu + c;
+#pragma unroll
+      for (int I = 0; I < T; ++I) fa[I] = U[offa + 16 * I];
+#pragma unroll
+      for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fb[I], fb[J], acc[tix<T>(I, J)]);
+    }
+#pragma unroll
+    for (int J = 0; J < T; ++J) {
+      const int idx = 16 * J + c;
+      const double v = U[uoff + idx];
+      augv[J] = (idx < N && q == 0) ? v : 0.0;
+    }
+  } else {
+    // lane (q, c) also sums u_k U[P_{16I+c}][k] over members k = q mod 4.
+    // (Single-buffered: a double-buffered form of this loop was miscompiled,
+    // its live MFMA accumulators being reused as load destinations.)
+    const int ksteps = (N + 3) >> 2;
+    int base[T];
+#pragma unroll
+    for (int I = 0; I < T; ++I) base[I] = L.pidx[16 * I + c] * ldu + q;
+    double vp[T];
+#pragma unroll
+    for (int I = 0; I < T; ++I) vp[I] = 0.0;
+    for (int ks = 0; ks < ksteps; ++ks) {
+      double f[T];
+#pragma unroll
+      for (int I = 0; I < T; ++I) f[I] = U[base[I] + 4 * ks];
+      const double uk = U[uoff + q + 4 * ks];
 #pragma unroll
       for (int I = 0; I < T; ++I) {
-        const double x = src[16 * I + c];
-        f[I] = k < p ? x : 0.0;
-      }
-    } else {
-      const int k = 4 * ks + q;
 #pragma unroll
-      for (int I = 0; I < T; ++I) {
-        const int a = 16 * I + c;
-        const int aa = a < p ? a : p - 1;
-        const double x = U[(int64_t)L.pidx[aa] * ldu + k];
-        f[I] = a < p ? x : 0.0;
+        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I], f[J], acc[tix<T>(I, J)]);
+        vp[I] = fma(f[I], uk, vp[I]);
       }
     }
 #pragma unroll
-    for (int I = 0; I < T; ++I)
-#pragma unroll
-      for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I], f[J], acc[tix<T>(I, J)]);
+    for (int I = 0; I < T; ++I) {
+      vp[I] += __shfl_xor(vp[I], 16, 64);
+      vp[I] += __shfl_xor(vp[I], 32, 64);
+      augv[I] = (16 * I + c < m && q == 0) ? vp[I] : 0.0;
+    }
   }
   // ridge on the diagonal, identity on the padding
 #pragma unroll
@@ -108,27 +162,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         const int idx = 16 * J + c;
         acc[tix<T>(J, J)][rr] = idx < m ? acc[tix<T>(J, J)][rr] + mu : 1.0;
       }
-  // ---- 2. right-hand side in row 0 of the extra tile row -------------------
-  if (!kform) {
-    for (int a = lane; a < p; a += 64) {
-      const double *ua = U + (int64_t)L.pidx[a] * ldu;
-      double s = 0.0;
-      for (int cc = 0; cc < N; ++cc) s += ua[cc] * u[cc];
-      L.vec[a] = s;
-    }
-    wave_lds_sync();
-  }
-  if (q == 0) {
-#pragma unroll
-    for (int J = 0; J < T; ++J) {
-      const int idx = 16 * J + c;
-      const double v = kform ? u[idx] : L.vec[idx < p ? idx : 0];
-      acc[tix<T>(T, J)][0] = idx < m ? v : 0.0;
-    }
-  }
-  wave_lds_sync();
 
   // ---- 3. blocked Cholesky of the bordered matrix -------------------------
+  // L.col holds column k of the current panel: element of row 16I + 4rr + q
+  // at 16I + 4q + rr; the bordering row sits at 16T.
 #pragma unroll
   for (int J = 0; J < T; ++J) {
 #pragma unroll
@@ -139,64 +176,77 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
         return;
       }
-      const double lkk = sqrt(piv);
-      const double inv = 1.0 / lkk;
+      const double inv = rsqrt_nr(piv);
+      const double lkk = piv * inv;
+      if (lane == 0) L.dinv[16 * J + kk] = inv;
       if (c == kk) {
 #pragma unroll
-        for (int I = J; I <= T; ++I) {
+        for (int I = J; I < T; ++I) {
           d4 v = acc[tix<T>(I, J)];
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr) v[rr] = (I == J && 4 * rr + q == kk) ? lkk : v[rr] * inv;
           acc[tix<T>(I, J)] = v;
-          *(d4 *)&L.col[16 * I + 4 * q] = v;   // element (16I + 4rr + q) stored at 16I + 4q + rr
+          *(d4 *)&L.col[16 * I + 4 * q] = v;
+        }
+        if (q == 0) {
+          augv[J] *= inv;
+          L.col[16 * T] = augv[J];
         }
       }
       wave_lds_sync();
       const double colv = L.col[16 * J + 4 * (c & 3) + (c >> 2)];
       const double cv = c > kk ? colv : 0.0;
 #pragma unroll
-      for (int I = J; I <= T; ++I) {
+      for (int I = J; I < T; ++I) {
         const d4 rowv = *(const d4 *)&L.col[16 * I + 4 * q];
         d4 v = acc[tix<T>(I, J)];
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) v[rr] -= rowv[rr] * cv;
         acc[tix<T>(I, J)] = v;
       }
+      augv[J] -= L.col[16 * T] * cv;
       wave_lds_sync();
     }
     if (J + 1 < T) {
-      // transpose the panel tiles below the diagonal into LDS (row-major, padded)
+      // transpose the panel tiles below the diagonal into LDS (row-major, padded);
+      // the bordering row becomes row 0 of the last buffer (rows 1..15 unused)
 #pragma unroll
-      for (int I = J + 1; I <= T; ++I) {
+      for (int I = J + 1; I < T; ++I) {
         double *tb = L.tile + (I - J - 1) * 16 * kTileLd;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) tb[(4 * rr + q) * kTileLd + c] = acc[tix<T>(I, J)][rr];
       }
+      double *tba = L.tile + (T - J - 1) * 16 * kTileLd;
+      if (q == 0) tba[c] = augv[J];
       wave_lds_sync();
 #pragma unroll
       for (int I2 = J + 1; I2 < T; ++I2) {
         const double *tb2 = L.tile + (I2 - J - 1) * 16 * kTileLd;
-        double fb[4];
+        double fbk[4];
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) fb[kc] = tb2[c * kTileLd + 4 * kc + q];
+        for (int kc = 0; kc < 4; ++kc) fbk[kc] = tb2[c * kTileLd + 4 * kc + q];
 #pragma unroll
-        for (int I = I2; I <= T; ++I) {
+        for (int I = I2; I < T; ++I) {
           const double *tb = L.tile + (I - J - 1) * 16 * kTileLd;
           d4 a = acc[tix<T>(I, I2)];
 #pragma unroll
-          for (int kc = 0; kc < 4; ++kc) a = mfma64(-tb[c * kTileLd + 4 * kc + q], fb[kc], a);
+          for (int kc = 0; kc < 4; ++kc) a = mfma64(-tb[c * kTileLd + 4 * kc + q], fbk[kc], a);
           acc[tix<T>(I, I2)] = a;
         }
+        d4 a = d4{augv[I2], 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) a = mfma64(c == 0 ? -tba[4 * kc + q] : 0.0, fbk[kc], a);
+        augv[I2] = a[0];
       }
       wave_lds_sync();
     }
   }
 
-  // ---- 4. back substitution L^T x = y (y = row 0 of the extra tile row) ---
+  // ---- 4. back substitution L^T x = y (y = the factored bordering row) ----
   double *y = L.vec;   // y then x, natural order
   if (q == 0) {
 #pragma unroll
-    for (int J = 0; J < T; ++J) y[16 * J + c] = acc[tix<T>(T, J)][0];
+    for (int J = 0; J < T; ++J) y[16 * J + c] = augv[J];
   }
   wave_lds_sync();
 #pragma unroll
@@ -210,8 +260,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     s += __shfl_xor(s, 16, 64);
     s += __shfl_xor(s, 32, 64);
     double t = y[16 * J + c] - s;        // replicated over q
-    // diagonal tile row-major into LDS: element (i, j) at i*17 + j
-    double *tb = L.tile;
+    double *tb = L.tile;                 // diagonal tile row-major: (i, j) at i*17 + j
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) tb[(4 * rr + q) * kTileLd + c] = acc[tix<T>(J, J)][rr];
     wave_lds_sync();
@@ -221,8 +270,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     double xc = 0.0;
 #pragma unroll
     for (int jj = 15; jj >= 0; --jj) {
-      const double ljj = tb[jj * kTileLd + jj];
-      const double xj = readlane_d(t, jj) / ljj;
+      const double xj = readlane_d(t, jj) * L.dinv[16 * J + jj];
       if (c == jj) xc = xj;
       if (c < jj) t -= lrow[jj] * xj;
     }
@@ -232,24 +280,53 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   }
 
   // ---- 5. coefficients and residual variance --------------------------------
+  // x (= w or beta) is zero beyond m, so the padded terms below vanish.
   double ss = 0.0;
-  if (kform) {
-    for (int a = lane; a < p; a += 64) {
-      const double *ua = U + (int64_t)L.pidx[a] * ldu;
+  if (KF) {
+    // beta_a = sum_k U[P_a][k] w_k: lane (q, c) takes predecessor 16g + c and
+    // members k = q mod 4; the four partial sums are then added across q.
+    double wq[4 * T];
+#pragma unroll
+    for (int j = 0; j < 4 * T; ++j) wq[j] = y[4 * j + q];
+    const int G = (p + 15) >> 4;
+    for (int g = 0; g < G; ++g) {
+      const int a = 16 * g + c;
+      const int off = L.pidx[a] * ldu + q;
       double b = 0.0;
-      for (int cc = 0; cc < N; ++cc) b += ua[cc] * y[cc];
-      tval[lo + a] = -b;
+#pragma unroll
+      for (int j = 0; j < 4 * T; ++j) b = fma(U[off + 4 * j], wq[j], b);
+      b += __shfl_xor(b, 16, 64);
+      b += __shfl_xor(b, 32, 64);
+      if (q == 0 && a < p) tval[lo + a] = -b;
     }
-    for (int cc = lane; cc < N; cc += 64) {
-      const double e = mu * y[cc];
-      ss += e * e;
+    if (q == 0) {
+#pragma unroll
+      for (int I = 0; I < T; ++I) {
+        const double e = mu * y[16 * I + c];
+        ss += e * e;
+      }
     }
   } else {
+    // eps_k = u_k - sum_a beta_a U[P_a][k]: lane (q, c) takes member 16I + c and
+    // predecessors a = q mod 4; the four partial sums are then added across q.
     for (int a = lane; a < p; a += 64) tval[lo + a] = -y[a];
-    for (int cc = lane; cc < N; cc += 64) {
-      double e = u[cc];
-      for (int a = 0; a < p; ++a) e -= y[a] * U[(int64_t)L.pidx[a] * ldu + cc];
-      ss += e * e;
+    double bq[4 * T];
+    int off[4 * T];
+#pragma unroll
+    for (int j = 0; j < 4 * T; ++j) {
+      bq[j] = y[4 * j + q];
+      off[j] = L.pidx[4 * j + q] * ldu + c;
+    }
+    for (int I = 0; 16 * I < N; ++I) {
+      double e = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4 * T; ++j) e = fma(bq[j], U[off[j] + 16 * I], e);
+      e += __shfl_xor(e, 16, 64);
+      e += __shfl_xor(e, 32, 64);
+      if (q == 0 && 16 * I + c < N) {
+        const double eps = U[uoff + 16 * I + c] - e;
+        ss += eps * eps;
+      }
     }
   }
   ss = wave_sum(ss);
@@ -260,62 +337,88 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   }
 }
 
-__global__ __launch_bounds__(256, 2) void k_fit_batched(const Block *__restrict__ blocks,
-                                                     const int32_t *__restrict__ fit_glob,
-                                                     const int32_t *__restrict__ fit_blk,
-                                                     const int64_t *__restrict__ row_ptr,
-                                                     const int32_t *__restrict__ col, const double *__restrict__ U,
-                                                     int ldu, int N, int64_t n_fit, double lam,
-                                                     double *__restrict__ tval, double *__restrict__ dvec,
-                                                     int32_t *status) {
-  __shared__ WaveLds lds[4];
+// waves per SIMD each kernel is compiled for (register budget 512 / occupancy)
+constexpr int occupancy_for(int T, bool KF) { return T <= 2 ? 4 : (T == 3 ? (KF ? 4 : 3) : (T == 4 && KF ? 3 : 2)); }
+
+template <int T, bool KF>
+__global__ __launch_bounds__(256, occupancy_for(T, KF)) void k_fit_batched(
+    const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
+    int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, double lam, double *__restrict__ tval,
+    double *__restrict__ dvec, int32_t *status) {
+  __shared__ WaveLds<T> lds[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + wave;
-  if (r >= n_fit) return;
-  WaveLds &L = lds[wave];
+  const int64_t idx = (int64_t)blockIdx.x * 4 + wave;
+  if (idx >= nrows) return;
+  const int64_t r = rows[idx];
+  WaveLds<T> &L = lds[wave];
   const Block B = blocks[fit_blk[r]];
   const int64_t lo = row_ptr[r];
   const int p = (int)(row_ptr[r + 1] - lo);
-  const double *u = U + (int64_t)fit_glob[r] * ldu;
-  const double mu = lam * (double)(N - 1);
-  for (int k = lane; k < p; k += 64) L.pidx[k] = fit_glob[B.row0 + col[lo + k]];
+  const int uoff = fit_glob[r] * ldu;
+  for (int k = lane; k < kMaxP + 8; k += 64) L.pidx[k] = k < p ? fit_glob[B.row0 + col[lo + k]] : zrow;
   wave_lds_sync();
-  if (p == 0) {
-    double s = 0.0;
-    for (int cc = lane; cc < N; cc += 64) s += u[cc] * u[cc];
-    s = wave_sum(s);
-    if (lane == 0) {
-      const double dd = s / (N - 1);
-      dvec[r] = dd;
-      if (!(dd > 0.0)) set_error(status, ENKFMC_ENONPOS_D, (int32_t)r);
-    }
-    return;
-  }
-  const bool kform = lam > 0.0 && p >= N;
-  if (!kform && lam == 0.0 && p >= N - 1) {
+  if (!KF && lam == 0.0 && p >= N - 1) {
     if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
     return;
   }
-  const int m = kform ? N : p;
-  const int T = (m + 15) >> 4;
-  switch (T) {
-    case 1: fit_row<1>(lane, r, p, N, kform, mu, U, ldu, u, L, tval, lo, dvec, status); break;
-    case 2: fit_row<2>(lane, r, p, N, kform, mu, U, ldu, u, L, tval, lo, dvec, status); break;
-    case 3: fit_row<3>(lane, r, p, N, kform, mu, U, ldu, u, L, tval, lo, dvec, status); break;
-    case 4: fit_row<4>(lane, r, p, N, kform, mu, U, ldu, u, L, tval, lo, dvec, status); break;
-    default: fit_row<5>(lane, r, p, N, kform, mu, U, ldu, u, L, tval, lo, dvec, status); break;
+  fit_row<T, KF>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, dvec, status);
+}
+
+// Regressions without predecessors: d = u^T u / (N - 1).
+__global__ __launch_bounds__(256) void k_fit_p0(const int32_t *__restrict__ fit_glob, const double *__restrict__ U,
+                                                int ldu, int N, const int32_t *__restrict__ rows, int64_t nrows,
+                                                double *__restrict__ dvec, int32_t *status) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + wave;
+  if (idx >= nrows) return;
+  const int64_t r = rows[idx];
+  const double *u = U + (int64_t)fit_glob[r] * ldu;
+  double s = 0.0;
+  for (int cc = lane; cc < N; cc += 64) s += u[cc] * u[cc];
+  s = wave_sum(s);
+  if (lane == 0) {
+    const double dd = s / (N - 1);
+    dvec[r] = dd;
+    if (!(dd > 0.0)) set_error(status, ENKFMC_ENONPOS_D, (int32_t)r);
   }
 }
 
-size_t fit_plain_lds(const enkfmc_plan *p);
+template <int T, bool KF>
+static void launch_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_fit_batched<T, KF>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d.blocks, d.fit_glob,
+                     d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam, d.tval, d.dvec,
+                     d.status);
+}
 
 hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s) {
-  // rows whose system exceeds 80 (N > 80 in the kernel form) or with more
-  // than 128 predecessors are outside this kernel's register budget
+  // systems beyond 80 (N > 80 in the kernel form) or more than 128
+  // predecessors exceed this kernel's register budget: plain kernel instead
   if (p->N > 16 * kMaxT || p->max_p > kMaxP) return launch_fit_plain(p, d, lam, s);
   phase_begin(p, ENKFMC_PH_FIT, s);
-  hipLaunchKernelGGL(k_fit_batched, dim3((unsigned)((p->n_fit + 3) / 4)), dim3(256), 0, s, d.blocks, d.fit_glob,
-                     d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, p->n_fit, lam, d.tval, d.dvec, d.status);
+  const int32_t *rows = d.fit_rows;
+  const int64_t *bo = p->bucket_off;   // bucket 0: p = 0, 1..5: p-form T, 6: p >= N
+  if (bo[1] > bo[0])
+    hipLaunchKernelGGL(k_fit_p0, dim3((unsigned)((bo[1] - bo[0] + 3) / 4)), dim3(256), 0, s, d.fit_glob, d.U, p->ldu,
+                       p->N, rows + bo[0], bo[1] - bo[0], d.dvec, d.status);
+  launch_bucket<1, false>(p, d, rows + bo[1], bo[2] - bo[1], lam, s);
+  launch_bucket<2, false>(p, d, rows + bo[2], bo[3] - bo[2], lam, s);
+  launch_bucket<3, false>(p, d, rows + bo[3], bo[4] - bo[3], lam, s);
+  launch_bucket<4, false>(p, d, rows + bo[4], bo[5] - bo[4], lam, s);
+  launch_bucket<5, false>(p, d, rows + bo[5], bo[6] - bo[5], lam, s);
+  const int64_t nk = bo[7] - bo[6];
+  if (lam > 0.0) {
+    switch ((p->N + 15) / 16) {   // kernel form: m = N
+      case 1: launch_bucket<1, true>(p, d, rows + bo[6], nk, lam, s); break;
+      case 2: launch_bucket<2, true>(p, d, rows + bo[6], nk, lam, s); break;
+      case 3: launch_bucket<3, true>(p, d, rows + bo[6], nk, lam, s); break;
+      case 4: launch_bucket<4, true>(p, d, rows + bo[6], nk, lam, s); break;
+      default: launch_bucket<5, true>(p, d, rows + bo[6], nk, lam, s); break;
+    }
+  } else {
+    launch_bucket<5, false>(p, d, rows + bo[6], nk, lam, s);   // p >= N without ridge: ENOTSPD
+  }
   phase_end(p, ENKFMC_PH_FIT, s);
   return hipGetLastError();
 }

@@ -20,7 +20,11 @@ __global__ __launch_bounds__(256) void k_anomaly(const TX *__restrict__ Xb, int6
                                                  double *__restrict__ mean, double *__restrict__ U) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
-  if (row >= n) return;
+  if (row >= n + 2) return;
+  if (row >= n) {  // zero pad rows after the n anomaly rows
+    for (int c = lane; c < ldu; c += 64) U[row * ldu + c] = 0.0;
+    return;
+  }
   const TX *x = Xb + row * ld;
   double s = 0.0;
   for (int c = lane; c < N; c += 64) s += (double)x[c];
@@ -32,7 +36,7 @@ __global__ __launch_bounds__(256) void k_anomaly(const TX *__restrict__ Xb, int6
 }
 
 hipError_t launch_anomaly(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, hipStream_t s) {
-  const dim3 grid((unsigned)((p->n + 3) / 4)), block(256);
+  const dim3 grid((unsigned)((p->n + 2 + 3) / 4)), block(256);
   phase_begin(p, ENKFMC_PH_ANOMALY, s);
   if (dtype == ENKFMC_F32)
     hipLaunchKernelGGL(k_anomaly<float>, grid, block, 0, s, (const float *)Xb, ld, p->n, p->N, p->ldu, d.mean, d.U);

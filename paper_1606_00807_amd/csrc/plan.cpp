@@ -126,6 +126,24 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
   for (int64_t gi = 0; gi < n; ++gi)
     if (p->interior_src[gi] < 0) { *err = "internal: component not covered by any interior"; return ENKFMC_EINVAL; }
 
+  // regressions grouped by size for the batched fit (stable within a group)
+  {
+    auto key = [&](int64_t r) {
+      const int64_t pp = p->row_ptr[r + 1] - p->row_ptr[r];
+      if (pp == 0) return 0;
+      if (pp >= N) return 6;
+      return (int)std::min<int64_t>((pp + 15) / 16, 5);
+    };
+    int64_t cnt[8] = {};
+    for (int64_t r = 0; r < n_fit; ++r) cnt[key(r) + 1]++;
+    for (int b = 0; b < 7; ++b) cnt[b + 1] += cnt[b];
+    for (int b = 0; b < 8; ++b) p->bucket_off[b] = cnt[b];
+    p->fit_rows.assign(n_fit, 0);
+    int64_t fill[8];
+    for (int b = 0; b < 8; ++b) fill[b] = cnt[b];
+    for (int64_t r = 0; r < n_fit; ++r) p->fit_rows[fill[key(r)]++] = (int32_t)r;
+  }
+
   // local observations, per block, observation number ascending (R5: whole extended box)
   std::vector<std::vector<int32_t>> bo(p->blocks.size()), br(p->blocks.size());
   const int32_t nxy = p->nx * p->ny;
@@ -255,6 +273,7 @@ void compute_layout(enkfmc_plan *p) {
   L.blocks = take(nb * sizeof(Block));
   L.fit_glob = take(nf * 4);
   L.fit_blk = take(nf * 4);
+  L.fit_rows = take(nf * 4);
   L.row_ptr = take((nf + 1) * 8);
   L.col = take(nz * 4);
   L.csc_ptr = take((nf + 1) * 8);
@@ -276,7 +295,7 @@ void compute_layout(enkfmc_plan *p) {
   L.tval = take(nz * 8);
   L.dvec = take(nf * 8);
   L.mean = take(n * 8);
-  L.U = take(n * (size_t)p->ldu * 8);
+  L.U = take((n + 2) * (size_t)p->ldu * 8);   // two trailing all-zero pad rows
   L.Z = take(nf * N * 8);
   L.F = take((size_t)p->sum_F * 8);
   L.S = take((size_t)p->sum_S * 8);

@@ -37,7 +37,7 @@ struct SubBox {
 
 // Offsets (bytes) of every device array inside the workspace.
 struct Layout {
-  size_t blocks, fit_glob, fit_blk, row_ptr, col, csc_ptr, csc_row, csc_nz, interior_src, bobs_o, bobs_row;
+  size_t blocks, fit_glob, fit_blk, fit_rows, row_ptr, col, csc_ptr, csc_row, csc_nz, interior_src, bobs_o, bobs_row;
   size_t g2f_ptr, g2f, o2b_ptr, o2b;
   size_t rt_ptr, rt_col, rt_slot, ct_ptr, ct_row, ct_slot;
   size_t tval, dvec, mean, U, Z, F, S, Q, W, aux1, aux2, aux3, red, tiles, tinv, status;
@@ -57,6 +57,8 @@ struct enkfmc_plan {
   std::vector<enkfmc::SubBox> subs;
   std::vector<enkfmc::Block> blocks;
   std::vector<int32_t> fit_glob, fit_blk;       // per fit row
+  std::vector<int32_t> fit_rows;                // fit rows grouped by regression size (see bucket_off)
+  int64_t bucket_off[8] = {};                   // 0: p = 0, 1..5: p < N with ceil(p/16), 6: p >= N
   std::vector<int64_t> row_ptr;                 // n_fit + 1, global CSR offsets
   std::vector<int32_t> col;                     // block-local predecessor rows
   std::vector<int64_t> csc_ptr;                 // n_fit + 1, transposed pattern
