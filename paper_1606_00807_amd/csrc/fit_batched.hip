@@ -52,13 +52,13 @@ __device__ inline double readlane_d(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Orders this wavefront's LDS accesses (lanes exchange values through LDS):
-// waits for the wavefront's outstanding LDS operations and keeps the
-// compiler from moving memory operations or other code across this point.
+// Orders this wavefront's LDS accesses (lanes exchange values through LDS).
+// LDS executes one wavefront's operations in issue order and returns them in
+// order, so a read issued after a write sees it; this barrier only keeps the
+// compiler from reordering memory operations across this point.
 __device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __asm__ __volatile__("" ::: "memory");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_sched_barrier(0);
 }
 
 // 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps
@@ -168,10 +168,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   // at 16I + 4q + rr; the bordering row sits at 16T.
 #pragma unroll
   for (int J = 0; J < T; ++J) {
+    // pivot of the panel's first column (after the trailing updates)
+    double piv = readlane_d(acc[tix<T>(J, J)][0], 0);
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
-      const int qk = kk & 3, rk = kk >> 2;
-      const double piv = readlane_d(acc[tix<T>(J, J)][rk], 16 * qk + kk);
       if (!(piv > 0.0)) {
         if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
         return;
@@ -193,6 +193,15 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
           L.col[16 * T] = augv[J];
         }
       }
+      // lookahead: the next pivot only needs L[k+1][k] and the not yet updated
+      // A[k+1][k+1]; computing it here takes the reciprocal square root off the
+      // path through the column broadcast (same fma as the update below)
+      if (kk + 1 < 16) {
+        const int q1 = (kk + 1) & 3, r1 = (kk + 1) >> 2;
+        const double lnext = readlane_d(acc[tix<T>(J, J)][r1], 16 * q1 + kk);
+        const double anext = readlane_d(acc[tix<T>(J, J)][r1], 16 * q1 + kk + 1);
+        piv = fma(-lnext, lnext, anext);
+      }
       wave_lds_sync();
       const double colv = L.col[16 * J + 4 * (c & 3) + (c >> 2)];
       const double cv = c > kk ? colv : 0.0;
@@ -201,10 +210,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         const d4 rowv = *(const d4 *)&L.col[16 * I + 4 * q];
         d4 v = acc[tix<T>(I, J)];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) v[rr] -= rowv[rr] * cv;
+        for (int rr = 0; rr < 4; ++rr) v[rr] = fma(-rowv[rr], cv, v[rr]);
         acc[tix<T>(I, J)] = v;
       }
-      augv[J] -= L.col[16 * T] * cv;
+      augv[J] = fma(-L.col[16 * T], cv, augv[J]);
       wave_lds_sync();
     }
     if (J + 1 < T) {
