@@ -179,6 +179,7 @@ enum {
   ENKFMC_PH_MAPBACK = 8,   /* X_a = X_b + Z on interior rows                       */
   ENKFMC_PH_BACKWARD = 9,  /* whole reverse pass                                   */
   ENKFMC_PH_TILES = 10,    /* dense 16x16 tiles of T and inverse diagonal tiles     */
+  ENKFMC_PH_FIT_KFORM = 11, /* kernel-form regressions (p >= N) alone, within FIT  */
   ENKFMC_PH_COUNT = 16
 };
 enkfmc_status enkfmc_set_timing(enkfmc_plan *p, int32_t enable);

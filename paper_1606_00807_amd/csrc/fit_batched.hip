@@ -418,6 +418,7 @@ hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStrea
   launch_bucket<5, false>(p, d, rows + bo[5], bo[6] - bo[5], lam, s);
   const int64_t nk = bo[7] - bo[6];
   if (lam > 0.0) {
+    if (nk > 0) phase_begin(p, ENKFMC_PH_FIT_KFORM, s);
     switch ((p->N + 15) / 16) {   // kernel form: m = N
       case 1: launch_bucket<1, true>(p, d, rows + bo[6], nk, lam, s); break;
       case 2: launch_bucket<2, true>(p, d, rows + bo[6], nk, lam, s); break;
@@ -425,6 +426,7 @@ hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStrea
       case 4: launch_bucket<4, true>(p, d, rows + bo[6], nk, lam, s); break;
       default: launch_bucket<5, true>(p, d, rows + bo[6], nk, lam, s); break;
     }
+    if (nk > 0) phase_end(p, ENKFMC_PH_FIT_KFORM, s);
   } else {
     launch_bucket<5, false>(p, d, rows + bo[6], nk, lam, s);   // p >= N without ridge: ENOTSPD
   }
