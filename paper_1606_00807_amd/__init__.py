@@ -5,3 +5,4 @@ libenkfmc.so (hand-written HIP for gfx950, C ABI in include/enkfmc.h).  This
 package is its thin binding: ``Plan`` (api.py) and the autograd wrapper.
 """
 from .api import EnkfmcError, Plan  # noqa: F401
+from .autograd import EnkfmcAnalysis, enkfmc_analysis  # noqa: F401

@@ -143,17 +143,23 @@ class Plan:
         out_dtype = out_dtype or torch.float64
         Xa = torch.empty((self.n, self.N), dtype=out_dtype, device=Xb.device)
         p, dt, ld = self._xb_args(Xb)
+        self._analysis_inputs = None
         check(self.lib.enkfmc_analyze(self._h, p, dt, ld, ctypes.c_void_p(Y.data_ptr()),
                                       ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(Xa.data_ptr()),
                                       F32 if out_dtype == torch.float32 else F64, SOLVE_DUAL, self._stream()))
+        # the reverse pass reads the same device copies of Y and r_diag
+        self._analysis_inputs = (Y, r)
         return Xa
 
-    def backward(self, Xb, Y, r_diag, dXa) -> Tuple:
-        """dL/dX_b, dL/dlog r, dL/dridge from dL/dX_a (after fit + analyze)."""
+    def backward(self, Xb, dXa) -> Tuple:
+        """dL/dX_b, dL/dlog r, dL/dridge from dL/dX_a, for the preceding
+        fit + analyze of this plan on the same X_b (derivation in
+        csrc/backward.hip)."""
         import torch
         self._check_xb(Xb)
-        Y = self._dev64(Y, (self.m, self.N), "Y")
-        r = self._dev64(r_diag, (self.m,), "r_diag")
+        if getattr(self, "_analysis_inputs", None) is None:
+            raise EnkfmcError(-7, "backward: needs the preceding fit + analyze")
+        Y, r = self._analysis_inputs
         g = self._dev64(dXa, (self.n, self.N), "dXa")
         dXb = torch.empty((self.n, self.N), dtype=torch.float64, device=Xb.device)
         dlogR = torch.empty((max(self.m, 1),), dtype=torch.float64, device=Xb.device)

@@ -226,12 +226,15 @@ __global__ __launch_bounds__(64) void k_dual_Q(const Block *__restrict__ blocks,
 }
 
 // Z = T^-1 (D (F Q)), forward over row tiles; one wavefront per (block, 16 member columns).
+// With V (n_fit x N) given it computes Z = T^-1 (D (V - F Q)) instead (the
+// adjoint solve reuses it).
 __global__ __launch_bounds__(64) void k_fwd_sweep(const Block *__restrict__ blocks, const int64_t *__restrict__ rt_ptr,
                                                   const int32_t *__restrict__ rt_col,
                                                   const int32_t *__restrict__ rt_slot,
                                                   const double *__restrict__ tiles, const double *__restrict__ tinv,
                                                   const double *__restrict__ F, const double *__restrict__ Q,
-                                                  const double *__restrict__ dvec, int N, double *__restrict__ Z) {
+                                                  const double *__restrict__ dvec, const double *__restrict__ V, int N,
+                                                  double *__restrict__ Z) {
   const Block B = blocks[blockIdx.x];
   const int cc = blockIdx.y;
   const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
@@ -252,7 +255,14 @@ __global__ __launch_bounds__(64) void k_fwd_sweep(const Block *__restrict__ bloc
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * R + 4 * r + q;
-      acc[r] *= row < B.n ? dvec[B.row0 + row] : 0.0;
+      const bool in = row < B.n;
+      const double dd = in ? dvec[B.row0 + row] : 0.0;
+      if (V) {
+        const double v = in && colok ? V[(B.row0 + row) * N + colj] : 0.0;
+        acc[r] = dd * (v - acc[r]);
+      } else {
+        acc[r] *= dd;
+      }
     }
     const int64_t s0 = rt_ptr[B.rt0 + R], s1 = rt_ptr[B.rt0 + R + 1];
     for (int64_t t = s0; t < s1; ++t) {
@@ -338,7 +348,7 @@ static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   }
   phase_begin(p, ENKFMC_PH_SWEEP, s);
   hipLaunchKernelGGL(k_fwd_sweep, dim3(nb, (N + 15) / 16), dim3(64), 0, s, d.blocks, d.rt_ptr, d.rt_col, d.rt_slot,
-                     d.tiles, d.tinv, d.F, d.Q, d.dvec, N, d.Z);
+                     d.tiles, d.tinv, d.F, d.Q, d.dvec, (const double *)nullptr, N, d.Z);
   phase_end(p, ENKFMC_PH_SWEEP, s);
   const int64_t tot = p->n * N;
   const dim3 g((unsigned)((tot + 255) / 256));
@@ -349,6 +359,13 @@ static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
     hipLaunchKernelGGL((k_mapback<TX, double>), g, dim3(256), 0, s, Xb, ld, d.interior_src, d.Z, p->n, N,
                        (double *)Xa);
   phase_end(p, ENKFMC_PH_MAPBACK, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const double *V, double *out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_fwd_sweep, dim3((unsigned)p->blocks.size(), (p->N + 15) / 16), dim3(64), 0, s, d.blocks,
+                     d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tinv, d.F, Q, d.dvec, V, p->N, out);
   return hipGetLastError();
 }
 

@@ -137,6 +137,7 @@ enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes,
   HIPCHK(put(p, L.g2f, p->g2f, s), "set_workspace");
   HIPCHK(put(p, L.o2b_ptr, p->o2b_ptr, s), "set_workspace");
   HIPCHK(put(p, L.o2b, p->o2b, s), "set_workspace");
+  HIPCHK(put(p, L.bobs_fit, p->bobs_fit, s), "set_workspace");
   HIPCHK(put(p, L.rt_ptr, p->rt_ptr, s), "set_workspace");
   HIPCHK(put(p, L.rt_col, p->rt_col, s), "set_workspace");
   HIPCHK(put(p, L.rt_slot, p->rt_slot, s), "set_workspace");
@@ -195,6 +196,8 @@ enkfmc_status enkfmc_analyze(enkfmc_plan *p, const void *Xb, int32_t dtype, int6
   st = finish(p, s, "analyze");
   if (st != ENKFMC_OK) return st;
   p->analyzed = 1;
+  p->an_y = Y;
+  p->an_r = r_diag;
   return ENKFMC_OK;
 }
 
@@ -205,8 +208,9 @@ enkfmc_status enkfmc_analyze_backward(enkfmc_plan *p, const void *Xb, int32_t dt
     return fail(ENKFMC_EINVAL, "analyze_backward: NULL argument");
   if (dtype != ENKFMC_F32 && dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "analyze_backward: bad dtype");
   if (ld < p->N) return fail(ENKFMC_EINVAL, "analyze_backward: ld < N");
-  if (!p->fitted || !p->analyzed || p->fit_xb != Xb)
+  if (!p->fitted || !p->analyzed || p->fit_xb != Xb || p->an_y != (const void *)Y || p->an_r != (const void *)r_diag)
     return fail(ENKFMC_ESTATE, "analyze_backward: needs the preceding fit + analyze on the same inputs");
+  if (p->N > 128) return fail(ENKFMC_EUNSUPPORTED, "analyze_backward: N > 128");
   hipStream_t s = (hipStream_t)stream;
   enkfmc_status st = begin(p, s, "analyze_backward");
   if (st != ENKFMC_OK) return st;

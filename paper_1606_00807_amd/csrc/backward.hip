@@ -1,9 +1,542 @@
-// Reverse-mode derivative of fit + analysis (placeholder).
+// Reverse-mode derivative of fit + local analysis.
+//
+// Forward, per (sub-domain, variable) block (eq. 11 per sub-domain):
+//   A Z = H^T R^-1 Delta,  A = T^T D^-1 T + H^T R^-1 H,  Delta = Y^s - H X_b,
+//   X_a = X_b + Z on interior rows;
+// per row i of T (eq. 1, ridge lam on the (N-1)-normalised Gram):
+//   G beta = c,  G = U_P U_P^T/(N-1) + lam I,  c = U_P u_i/(N-1),
+//   eps = u_i - U_P^T beta,  d_i = eps^T eps/(N-1),  T_{i,P} = -beta,
+// with u the ensemble anomalies of eq. (5).
+//
+// Reverse pass, given Gbar = dL/dX_a:
+//   Zbar = Gbar on interior rows, 0 on halo rows.
+//   W = A^-1 Zbar through the dual form (Woodbury, as eqs. 12-13):
+//     V = T^-T Zbar,  P = S^-1 (F^T D V),  W = T^-1 D (V - F P),
+//     with F = T^-T H^T and S = R + F^T D F (Cholesky kept by the analysis),
+//     since H T^-1 = F^T.
+//   Observations:  dlog r_o = (1/r_o) W_j . (Z_j - Delta_o),
+//                  dX_b[obs_o] -= W_j / r_o                  (j = local row of o).
+//   Factors (Abar = -W Z^T, symmetric part):
+//     Dbar_i     = d_i^-2 (T W)_i . (T Z)_i
+//     betabar_iq = [(T Z)_i . W_q + (T W)_i . Z_q] / d_i      (q in P(i))
+//   Regression of row i, recomputing its Gram and Cholesky:
+//     epsbar = 2 Dbar_i eps/(N-1),  b = betabar - U_P epsbar,  s = G^-1 b,
+//     lambar_i = -s . beta,  g = U_P^T s,
+//     e1_i = eps/(N-1),  e2_i = -(g/(N-1) + epsbar)
+//   so that Ubar_q = sum over rows i with q in P(i) of (s_iq e1_i + beta_iq e2_i)
+//   and ubar_i gets -e2_i.  Anomalies (eq. 5): dX_b += Ubar - mean_members(Ubar).
+// Every sum over sub-domains (overlapping halos) and over observations is a
+// gather in a fixed order, so the result is bitwise repeatable.
 #include "device.h"
 
 namespace enkfmc {
-hipError_t launch_backward(enkfmc_plan *, const Dev &, const void *, int32_t, int64_t, const double *, const double *,
-                           double, const double *, double *, double *, double *, hipStream_t) {
-  return hipErrorNotSupported;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// LDS written by some lanes of a wavefront and read by others: a wavefront
+// executes its LDS instructions in order, so only the compiler must not move
+// them across this point.
+__device__ inline void wave_lds_sync() {
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
 }
+
+// Zbar of fit row f: the output gradient of its component if f is the row that
+// maps back onto it, else 0.
+__device__ inline double zbar_of(const int32_t *fit_glob, const int32_t *interior_src, const double *dXa, int N,
+                                 int64_t f, int col) {
+  const int g = fit_glob[f];
+  return interior_src[g] == f ? dXa[(int64_t)g * N + col] : 0.0;
+}
+
+// V = T^-T Zbar, backward over row tiles; one wavefront per (block, 16 member columns).
+__global__ __launch_bounds__(64) void k_adj_bwd_sweep(const Block *__restrict__ blocks,
+                                                      const int64_t *__restrict__ ct_ptr,
+                                                      const int32_t *__restrict__ ct_row,
+                                                      const int32_t *__restrict__ ct_slot,
+                                                      const int32_t *__restrict__ fit_glob,
+                                                      const int32_t *__restrict__ interior_src,
+                                                      const double *__restrict__ tiles,
+                                                      const double *__restrict__ tinv, const double *__restrict__ dXa,
+                                                      int N, double *__restrict__ V) {
+  const Block B = blocks[blockIdx.x];
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int colj = 16 * blockIdx.y + c;
+  const bool colok = colj < N;
+  double *Vb = V + B.row0 * N;
+  for (int C = B.nrt - 1; C >= 0; --C) {
+    d4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * C + 4 * r + q;
+      acc[r] = (row < B.n && colok) ? zbar_of(fit_glob, interior_src, dXa, N, B.row0 + row, colj) : 0.0;
+    }
+    const int64_t s0 = ct_ptr[B.rt0 + C], s1 = ct_ptr[B.rt0 + C + 1];
+    for (int64_t t = s0; t < s1; ++t) {
+      const int R = ct_row[t];
+      const double *Tt = tiles + (int64_t)ct_slot[t] * 256;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        const int row = 16 * R + 4 * kc + q;
+        const double v = (row < B.n && colok) ? Vb[(int64_t)row * N + colj] : 0.0;
+        acc = mfma64(-Tt[(4 * kc + q) * 16 + c], v, acc);
+      }
+    }
+    const double *Ti = tinv + (B.rt0 + C) * 256;
+    d4 out = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) out = mfma64(Ti[(4 * kc + q) * 16 + c], acc[kc], out);
+    if (colok) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * C + 4 * r + q;
+        if (row < B.n) Vb[(int64_t)row * N + colj] = out[r];
+      }
+    }
+  }
+}
+
+// P = F^T D V (ldf x N per block); one wavefront per (block, 16 member columns).
+__global__ __launch_bounds__(64) void k_adj_ftdv(const Block *__restrict__ blocks, const double *__restrict__ F,
+                                                 const double *__restrict__ dvec, const double *__restrict__ V, int N,
+                                                 double *__restrict__ P) {
+  constexpr int kMaxTiles = 8;
+  const Block B = blocks[blockIdx.x];
+  if (B.m == 0) return;
+  const int TI = B.ldf >> 4;
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int colj = 16 * blockIdx.y + c;
+  const bool colok = colj < N;
+  const int ldf = B.ldf;
+  const double *Fb = F + B.F0;
+  const double *Vb = V + B.row0 * N;
+  d4 acc[kMaxTiles];
+#pragma unroll
+  for (int I = 0; I < kMaxTiles; ++I) acc[I] = d4{0.0, 0.0, 0.0, 0.0};
+  const int ksteps = 4 * B.nrt;
+  for (int ks = 0; ks < ksteps; ++ks) {
+    const int k = 4 * ks + q;
+    const bool in = k < B.n && colok;
+    const double b = in ? dvec[B.row0 + k] * Vb[(int64_t)k * N + colj] : 0.0;
+    const double *Fk = Fb + (int64_t)k * ldf + c;
+#pragma unroll
+    for (int I = 0; I < kMaxTiles; ++I)
+      if (I < TI) acc[I] = mfma64(Fk[16 * I], b, acc[I]);
+  }
+  if (!colok) return;
+  double *Pb = P + B.Q0;
+#pragma unroll
+  for (int I = 0; I < kMaxTiles; ++I) {
+    if (I < TI) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Pb[(int64_t)(16 * I + 4 * r + q) * N + colj] = acc[I][r];
+    }
+  }
+}
+
+// P <- S^-1 P with the Cholesky factor the analysis left in S; one lane per member.
+__global__ __launch_bounds__(64) void k_adj_solve_S(const Block *__restrict__ blocks, const double *__restrict__ S,
+                                                    int N, double *__restrict__ P) {
+  const Block B = blocks[blockIdx.x];
+  const int c = blockIdx.y * 64 + threadIdx.x;
+  if (c >= N || B.m == 0) return;
+  const int m = B.m, lds = B.ldf;
+  const double *L = S + B.S0;
+  double *x = P + B.Q0;
+  for (int a = 0; a < m; ++a) {
+    double acc = x[(int64_t)a * N + c];
+    for (int b = 0; b < a; ++b) acc -= L[(int64_t)a * lds + b] * x[(int64_t)b * N + c];
+    x[(int64_t)a * N + c] = acc / L[(int64_t)a * lds + a];
+  }
+  for (int a = m - 1; a >= 0; --a) {
+    double acc = x[(int64_t)a * N + c];
+    for (int b = a + 1; b < m; ++b) acc -= L[(int64_t)b * lds + a] * x[(int64_t)b * N + c];
+    x[(int64_t)a * N + c] = acc / L[(int64_t)a * lds + a];
+  }
+  for (int a = m; a < lds; ++a) x[(int64_t)a * N + c] = 0.0;
+}
+
+// Dbar_i and betabar_i of every fit row; one wavefront per row, N <= 128.
+__global__ __launch_bounds__(256) void k_adj_factor_bar(const Block *__restrict__ blocks,
+                                                        const int32_t *__restrict__ fit_blk,
+                                                        const int64_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const double *__restrict__ tval,
+                                                        const double *__restrict__ dvec, const double *__restrict__ Z,
+                                                        const double *__restrict__ W, int64_t n_fit, int N,
+                                                        double *__restrict__ dbar, double *__restrict__ bbar) {
+  __shared__ double sa[4][128], sb[4][128];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+  if (r >= n_fit) return;
+  const Block B = blocks[fit_blk[r]];
+  const int64_t lo = row_ptr[r];
+  const int p = (int)(row_ptr[r + 1] - lo);
+  const double d = dvec[r];
+  double tz[2], tw[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int cc = lane + 64 * h;
+    tz[h] = cc < N ? Z[r * N + cc] : 0.0;
+    tw[h] = cc < N ? W[r * N + cc] : 0.0;
+  }
+  for (int k = 0; k < p; ++k) {
+    const int64_t f = B.row0 + col[lo + k];
+    const double t = tval[lo + k];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cc = lane + 64 * h;
+      if (cc < N) {
+        tz[h] = fma(t, Z[f * N + cc], tz[h]);
+        tw[h] = fma(t, W[f * N + cc], tw[h]);
+      }
+    }
+  }
+  const double s = wave_sum(tz[0] * tw[0] + tz[1] * tw[1]);
+  if (lane == 0) dbar[r] = s / (d * d);
+  const double inv = 1.0 / d;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    sa[wave][lane + 64 * h] = tz[h] * inv;
+    sb[wave][lane + 64 * h] = tw[h] * inv;
+  }
+  wave_lds_sync();
+  // 16 lanes per predecessor, four predecessors at a time
+  const int g = lane >> 4, l16 = lane & 15;
+  for (int k0 = 0; k0 < p; k0 += 4) {
+    const int k = k0 + g;
+    double acc = 0.0;
+    if (k < p) {
+      const int64_t f = B.row0 + col[lo + k];
+      for (int cc = l16; cc < N; cc += 16) acc += sa[wave][cc] * W[f * N + cc] + sb[wave][cc] * Z[f * N + cc];
+    }
+    acc += __shfl_xor(acc, 8, 16);
+    acc += __shfl_xor(acc, 4, 16);
+    acc += __shfl_xor(acc, 2, 16);
+    acc += __shfl_xor(acc, 1, 16);
+    if (k < p && l16 == 0) bbar[lo + k] = acc;
+  }
+}
+
+// Solve M x = v in place with the lower Cholesky factor of M in LDS (m x m).
+__device__ inline void chol_solve_lds(const double *G, int m, double *v) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < m; ++k) {
+    if (tid == 0) v[k] /= G[k * m + k];
+    __syncthreads();
+    const double yk = v[k];
+    for (int i = k + 1 + tid; i < m; i += 256) v[i] -= G[i * m + k] * yk;
+    __syncthreads();
+  }
+  for (int k = m - 1; k >= 0; --k) {
+    if (tid == 0) v[k] /= G[k * m + k];
+    __syncthreads();
+    const double xk = v[k];
+    for (int i = tid; i < k; i += 256) v[i] -= G[k * m + i] * xk;
+    __syncthreads();
+  }
+}
+
+// Adjoint of each regression: one 256-thread workgroup per fit row.  Reads
+// betabar from sb_io and overwrites it with s; writes e1, e2 (n_fit x N) and
+// the row's share of dL/dlam.
+__global__ __launch_bounds__(256) void k_adj_regress(const Block *__restrict__ blocks,
+                                                     const int32_t *__restrict__ fit_glob,
+                                                     const int32_t *__restrict__ fit_blk,
+                                                     const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col, const double *__restrict__ U,
+                                                     int ldu, int N, int max_p, double lam,
+                                                     const double *__restrict__ tval, const double *__restrict__ dbar,
+                                                     double *__restrict__ sb_io, double *__restrict__ e1,
+                                                     double *__restrict__ e2, double *__restrict__ lam_row,
+                                                     int32_t *status) {
+  extern __shared__ double smem[];
+  __shared__ int bad;
+  const int64_t r = blockIdx.x;
+  const int tid = threadIdx.x;
+  const Block B = blocks[fit_blk[r]];
+  const int64_t lo = row_ptr[r];
+  const int p = (int)(row_ptr[r + 1] - lo);
+  const double *u = U + (int64_t)fit_glob[r] * ldu;
+  const double mu = lam * (double)(N - 1);
+  const double nm1 = (double)(N - 1);
+  const bool kform = lam > 0.0 && p >= N;
+  const int m = kform ? N : p;
+  const int vl = N > max_p ? N : max_p;
+  double *G = smem;                         // N*N
+  double *v = G + (size_t)N * N;            // vl: right-hand sides / solutions
+  double *eps = v + vl;                     // N
+  double *ebar = eps + N;                   // N
+  double *bb = ebar + N;                    // vl: betabar - U_P epsbar, then s
+  double *beta = bb + vl;                   // max_p
+  double *red = beta + max_p;               // 8
+  int *pidx = (int *)(red + 8);             // max_p
+  if (tid == 0) bad = 0;
+  for (int k = tid; k < p; k += 256) {
+    pidx[k] = fit_glob[B.row0 + col[lo + k]];
+    beta[k] = -tval[lo + k];
+  }
+  __syncthreads();
+  const double Db = dbar[r];
+  if (p == 0) {
+    for (int c = tid; c < N; c += 256) {
+      const double ec = 2.0 * Db * u[c] / nm1;
+      e1[r * N + c] = u[c] / nm1;
+      e2[r * N + c] = -ec;
+    }
+    if (tid == 0) lam_row[r] = 0.0;
+    return;
+  }
+  // Gram (lower triangle), as the forward fit forms it
+  if (kform) {
+    for (int idx = tid; idx < m * m; idx += 256) {
+      const int a = idx / m, b = idx % m;
+      if (b > a) continue;
+      double s = 0.0;
+      for (int q = 0; q < p; ++q) {
+        const double *uq = U + (int64_t)pidx[q] * ldu;
+        s += uq[a] * uq[b];
+      }
+      G[a * m + b] = s + (a == b ? mu : 0.0);
+    }
+  } else {
+    for (int idx = tid; idx < m * m; idx += 256) {
+      const int a = idx / m, b = idx % m;
+      if (b > a) continue;
+      const double *ua = U + (int64_t)pidx[a] * ldu, *ub = U + (int64_t)pidx[b] * ldu;
+      double s = 0.0;
+      for (int c = 0; c < N; ++c) s += ua[c] * ub[c];
+      G[a * m + b] = s + (a == b ? mu : 0.0);
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    if (tid == 0) {
+      const double piv = G[k * m + k];
+      if (!(piv > 0.0)) bad = 1;
+      else G[k * m + k] = sqrt(piv);
+    }
+    __syncthreads();
+    if (bad) {
+      if (tid == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
+      return;
+    }
+    const double lkk = G[k * m + k];
+    for (int i = k + 1 + tid; i < m; i += 256) G[i * m + k] /= lkk;
+    __syncthreads();
+    const int t = m - k - 1;
+    for (int idx = tid; idx < t * t; idx += 256) {
+      const int i = k + 1 + idx / t, j = k + 1 + idx % t;
+      if (j <= i) G[i * m + j] -= G[i * m + k] * G[j * m + k];
+    }
+    __syncthreads();
+  }
+  // residual eps (kernel form: eps = mu w with (U_P^T U_P + mu I) w = u)
+  if (kform) {
+    for (int c = tid; c < N; c += 256) v[c] = u[c];
+    __syncthreads();
+    chol_solve_lds(G, m, v);
+    for (int c = tid; c < N; c += 256) eps[c] = mu * v[c];
+  } else {
+    for (int c = tid; c < N; c += 256) {
+      double e = u[c];
+      for (int a = 0; a < p; ++a) e -= beta[a] * U[(int64_t)pidx[a] * ldu + c];
+      eps[c] = e;
+    }
+  }
+  __syncthreads();
+  for (int c = tid; c < N; c += 256) ebar[c] = 2.0 * Db * eps[c] / nm1;
+  __syncthreads();
+  for (int a = tid; a < p; a += 256) {
+    const double *ua = U + (int64_t)pidx[a] * ldu;
+    double s = sb_io[lo + a];
+    for (int c = 0; c < N; ++c) s -= ua[c] * ebar[c];
+    bb[a] = s;
+  }
+  __syncthreads();
+  // s = G^-1 bb with G = (U_P U_P^T + mu I)/(N-1)
+  if (kform) {
+    // (U_P U_P^T + mu I)^-1 = (1/mu) [I - U_P (U_P^T U_P + mu I)^-1 U_P^T]
+    for (int c = tid; c < N; c += 256) {
+      double t = 0.0;
+      for (int a = 0; a < p; ++a) t += U[(int64_t)pidx[a] * ldu + c] * bb[a];
+      v[c] = t;
+    }
+    __syncthreads();
+    chol_solve_lds(G, m, v);
+    for (int a = tid; a < p; a += 256) {
+      const double *ua = U + (int64_t)pidx[a] * ldu;
+      double t = 0.0;
+      for (int c = 0; c < N; ++c) t += ua[c] * v[c];
+      bb[a] = nm1 / mu * (bb[a] - t);
+    }
+  } else {
+    for (int a = tid; a < p; a += 256) v[a] = bb[a];
+    __syncthreads();
+    chol_solve_lds(G, m, v);
+    for (int a = tid; a < p; a += 256) bb[a] = nm1 * v[a];
+  }
+  __syncthreads();
+  double ls = 0.0;
+  for (int a = tid; a < p; a += 256) {
+    ls -= bb[a] * beta[a];
+    sb_io[lo + a] = bb[a];
+  }
+  ls = block_sum256(ls, red);
+  if (tid == 0) lam_row[r] = ls;
+  for (int c = tid; c < N; c += 256) {
+    double g = 0.0;
+    for (int a = 0; a < p; ++a) g += U[(int64_t)pidx[a] * ldu + c] * bb[a];
+    e1[r * N + c] = eps[c] / nm1;
+    e2[r * N + c] = -(g / nm1 + ebar[c]);
+  }
+}
+
+size_t adj_regress_lds(const enkfmc_plan *p) {
+  const int N = p->N, mp = p->max_p, vl = N > mp ? N : mp;
+  return (size_t)N * N * 8 + (size_t)(2 * vl + 2 * N + mp + 8) * 8 + (size_t)mp * 4 + 16;
+}
+
+// dX_b of every component: the direct term Gbar, plus the anomaly projection
+// of Ubar gathered over the fit rows of the component (sub-domain order) and
+// their successors (CSC order).  One wavefront per component, N <= 128.
+__global__ __launch_bounds__(256) void k_adj_gather(const Block *__restrict__ blocks,
+                                                    const int32_t *__restrict__ fit_blk,
+                                                    const int64_t *__restrict__ g2f_ptr,
+                                                    const int32_t *__restrict__ g2f,
+                                                    const int64_t *__restrict__ csc_ptr,
+                                                    const int32_t *__restrict__ csc_row,
+                                                    const int32_t *__restrict__ csc_nz,
+                                                    const double *__restrict__ tval, const double *__restrict__ sv,
+                                                    const double *__restrict__ e1, const double *__restrict__ e2,
+                                                    const double *__restrict__ dXa, int64_t n, int N,
+                                                    double *__restrict__ dXb) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + wave;
+  if (j >= n) return;
+  double ub[2] = {0.0, 0.0};
+  for (int64_t t = g2f_ptr[j]; t < g2f_ptr[j + 1]; ++t) {
+    const int64_t f = g2f[t];
+    const Block B = blocks[fit_blk[f]];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cc = lane + 64 * h;
+      if (cc < N) ub[h] -= e2[f * N + cc];
+    }
+    for (int64_t sl = csc_ptr[f]; sl < csc_ptr[f + 1]; ++sl) {
+      const int64_t i = B.row0 + csc_row[sl];
+      const int64_t k = B.nz0 + csc_nz[sl];
+      const double s = sv[k], tv = tval[k];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int cc = lane + 64 * h;
+        if (cc < N) ub[h] += s * e1[i * N + cc] - tv * e2[i * N + cc];
+      }
+    }
+  }
+  const double mean = wave_sum(ub[0] + ub[1]) / N;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int cc = lane + 64 * h;
+    if (cc < N) dXb[j * N + cc] = dXa[j * N + cc] + (ub[h] - mean);
+  }
+}
+
+// Observation terms: dlog r_o and the innovation's -W_j/r_o on dX_b[obs_o].
+// One wavefront per observation; its block entries in block order.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_adj_obs(const int64_t *__restrict__ o2b_ptr, const int32_t *__restrict__ o2b,
+                                                 const int32_t *__restrict__ bobs_fit,
+                                                 const int32_t *__restrict__ fit_glob, const double *__restrict__ Z,
+                                                 const double *__restrict__ W, const double *__restrict__ Y,
+                                                 const TX *__restrict__ Xb, int64_t ld,
+                                                 const double *__restrict__ r_diag, int64_t m, int N,
+                                                 double *__restrict__ dXb, double *__restrict__ dlogR) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t o = (int64_t)blockIdx.x * 4 + wave;
+  if (o >= m) return;
+  const int64_t e0 = o2b_ptr[o], e1 = o2b_ptr[o + 1];
+  const double ro = r_diag[o];
+  double dl = 0.0, aw[2] = {0.0, 0.0};
+  int64_t g = -1;
+  for (int64_t e = e0; e < e1; ++e) {
+    const int64_t f = bobs_fit[o2b[e]];
+    g = fit_glob[f];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cc = lane + 64 * h;
+      if (cc < N) {
+        const double w = W[f * N + cc];
+        const double delta = Y[o * N + cc] - (double)Xb[g * ld + cc];
+        dl += w * (Z[f * N + cc] - delta);
+        aw[h] += w;
+      }
+    }
+  }
+  dl = wave_sum(dl);
+  if (lane == 0) dlogR[o] = dl / ro;
+  if (g < 0) return;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int cc = lane + 64 * h;
+    if (cc < N) dXb[g * N + cc] -= aw[h] / ro;
+  }
+}
+
+// dL/dlam = sum of the rows' shares, in a fixed order.
+__global__ __launch_bounds__(256) void k_adj_lambda(const double *__restrict__ lam_row, int64_t n_fit,
+                                                    double *__restrict__ dridge) {
+  __shared__ double red[8];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n_fit; i += 256) s += lam_row[i];
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) dridge[0] = s;
+}
+
+template <typename TX>
+static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int64_t ld, const double *Y,
+                                 const double *r_diag, double lam, const double *dXa, double *dXb, double *dlogR,
+                                 double *dridge, hipStream_t s) {
+  const unsigned nb = (unsigned)p->blocks.size();
+  const int N = p->N;
+  const unsigned ct = (unsigned)((N + 15) / 16);
+  phase_begin(p, ENKFMC_PH_BACKWARD, s);
+  double *V = d.aux1;
+  hipLaunchKernelGGL(k_adj_bwd_sweep, dim3(nb, ct), dim3(64), 0, s, d.blocks, d.ct_ptr, d.ct_row, d.ct_slot,
+                     d.fit_glob, d.interior_src, d.tiles, d.tinv, dXa, N, V);
+  if (p->max_bm > 0) {
+    hipLaunchKernelGGL(k_adj_ftdv, dim3(nb, ct), dim3(64), 0, s, d.blocks, d.F, d.dvec, (const double *)V, N, d.P);
+    hipLaunchKernelGGL(k_adj_solve_S, dim3(nb, (N + 63) / 64), dim3(64), 0, s, d.blocks, d.S, N, d.P);
+  }
+  hipError_t e = launch_fwd_sweep(p, d, d.P, V, d.W, s);
+  if (e != hipSuccess) return e;
+  const unsigned gr = (unsigned)((p->n_fit + 3) / 4);
+  hipLaunchKernelGGL(k_adj_factor_bar, dim3(gr), dim3(256), 0, s, d.blocks, d.fit_blk, d.row_ptr, d.col, d.tval,
+                     d.dvec, d.Z, d.W, p->n_fit, N, d.dbar, d.aux3);
+  const size_t lds = adj_regress_lds(p);
+  e = hipFuncSetAttribute((const void *)k_adj_regress, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_regress, dim3((unsigned)p->n_fit), dim3(256), lds, s, d.blocks, d.fit_glob, d.fit_blk,
+                     d.row_ptr, d.col, d.U, p->ldu, N, p->max_p, lam, d.tval, d.dbar, d.aux3, d.aux1, d.aux2, d.red,
+                     d.status);
+  hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)((p->n + 3) / 4)), dim3(256), 0, s, d.blocks, d.fit_blk, d.g2f_ptr,
+                     d.g2f, d.csc_ptr, d.csc_row, d.csc_nz, d.tval, d.aux3, d.aux1, d.aux2, dXa, p->n, N, dXb);
+  if (p->m > 0)
+    hipLaunchKernelGGL(k_adj_obs<TX>, dim3((unsigned)((p->m + 3) / 4)), dim3(256), 0, s, d.o2b_ptr, d.o2b,
+                       d.bobs_fit, d.fit_glob, d.Z, d.W, Y, Xb, ld, r_diag, p->m, N, dXb, dlogR);
+  hipLaunchKernelGGL(k_adj_lambda, dim3(1), dim3(256), 0, s, d.red, p->n_fit, dridge);
+  phase_end(p, ENKFMC_PH_BACKWARD, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, const double *Y,
+                           const double *r_diag, double lam, const double *dXa, double *dXb, double *dlogR,
+                           double *dridge, hipStream_t s) {
+  if (dtype == ENKFMC_F32)
+    return backward_typed(p, d, (const float *)Xb, ld, Y, r_diag, lam, dXa, dXb, dlogR, dridge, s);
+  return backward_typed(p, d, (const double *)Xb, ld, Y, r_diag, lam, dXa, dXb, dlogR, dridge, s);
+}
+
 }  // namespace enkfmc

@@ -18,11 +18,11 @@ struct Dev {
   const int64_t *g2f_ptr;
   const int32_t *g2f;
   const int64_t *o2b_ptr;
-  const int32_t *o2b;
+  const int32_t *o2b, *bobs_fit;
   const int64_t *rt_ptr, *ct_ptr;
   const int32_t *rt_col, *rt_slot, *ct_row, *ct_slot;
   double *tiles, *tinv;
-  double *tval, *dvec, *mean, *U, *Z, *F, *S, *Q, *W, *aux1, *aux2, *aux3, *red;
+  double *tval, *dvec, *mean, *U, *Z, *F, *S, *Q, *P, *W, *aux1, *aux2, *aux3, *dbar, *red;
   int32_t *status;
 };
 
@@ -46,6 +46,7 @@ inline Dev make_dev(enkfmc_plan *p) {
   d.g2f = (const int32_t *)(w + L.g2f);
   d.o2b_ptr = (const int64_t *)(w + L.o2b_ptr);
   d.o2b = (const int32_t *)(w + L.o2b);
+  d.bobs_fit = (const int32_t *)(w + L.bobs_fit);
   d.rt_ptr = (const int64_t *)(w + L.rt_ptr);
   d.rt_col = (const int32_t *)(w + L.rt_col);
   d.rt_slot = (const int32_t *)(w + L.rt_slot);
@@ -62,10 +63,12 @@ inline Dev make_dev(enkfmc_plan *p) {
   d.F = (double *)(w + L.F);
   d.S = (double *)(w + L.S);
   d.Q = (double *)(w + L.Q);
+  d.P = (double *)(w + L.P);
   d.W = (double *)(w + L.W);
   d.aux1 = (double *)(w + L.aux1);
   d.aux2 = (double *)(w + L.aux2);
   d.aux3 = (double *)(w + L.aux3);
+  d.dbar = (double *)(w + L.dbar);
   d.red = (double *)(w + L.red);
   d.status = (int32_t *)(w + L.status);
   return d;
@@ -110,6 +113,8 @@ hipError_t launch_anomaly(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t 
 hipError_t launch_fit_plain(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
 hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
 hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s);
+hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const double *V, double *out,
+                            hipStream_t s);
 hipError_t launch_analysis_dual(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld,
                                 const double *Y, const double *r_diag, void *Xa, int32_t out_dtype, hipStream_t s);
 hipError_t launch_backward(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, const double *Y,

@@ -166,7 +166,7 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
       br[b].push_back((l * sb.BY + (lat - sb.ys)) * sb.BX + ix);
     }
   }
-  p->bobs_o.clear(); p->bobs_row.clear();
+  p->bobs_o.clear(); p->bobs_row.clear(); p->bobs_fit.clear();
   p->o2b_ptr.assign(m + 1, 0);
   int64_t sumF = 0, sumS = 0, sumQ = 0;
   for (size_t b = 0; b < p->blocks.size(); ++b) {
@@ -181,6 +181,7 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
     for (size_t t = 0; t < bo[b].size(); ++t) {
       p->bobs_o.push_back(bo[b][t]);
       p->bobs_row.push_back(br[b][t]);
+      p->bobs_fit.push_back((int32_t)(B.row0 + br[b][t]));
       p->o2b_ptr[bo[b][t] + 1]++;
     }
   }
@@ -286,6 +287,7 @@ void compute_layout(enkfmc_plan *p) {
   L.g2f = take(nf * 4);
   L.o2b_ptr = take((m + 1) * 8);
   L.o2b = take(ml * 4);
+  L.bobs_fit = take(ml * 4);
   L.rt_ptr = take((size_t)(p->n_rt + 1) * 8);
   L.rt_col = take(p->rt_col.size() * 4);
   L.rt_slot = take(p->rt_slot.size() * 4);
@@ -300,10 +302,12 @@ void compute_layout(enkfmc_plan *p) {
   L.F = take((size_t)p->sum_F * 8);
   L.S = take((size_t)p->sum_S * 8);
   L.Q = take((size_t)p->sum_Q * 8);
+  L.P = take((size_t)p->sum_Q * 8);
   L.W = take(nf * N * 8);
   L.aux1 = take(nf * N * 8);
   L.aux2 = take(nf * N * 8);
   L.aux3 = take(nz * 8);
+  L.dbar = take(nf * 8);
   L.red = take(nf * 8 + 64);
   L.tiles = take((size_t)p->n_slots * 256 * 8);
   L.tinv = take((size_t)p->n_rt * 256 * 8);

@@ -38,9 +38,9 @@ struct SubBox {
 // Offsets (bytes) of every device array inside the workspace.
 struct Layout {
   size_t blocks, fit_glob, fit_blk, fit_rows, row_ptr, col, csc_ptr, csc_row, csc_nz, interior_src, bobs_o, bobs_row;
-  size_t g2f_ptr, g2f, o2b_ptr, o2b;
+  size_t g2f_ptr, g2f, o2b_ptr, o2b, bobs_fit;
   size_t rt_ptr, rt_col, rt_slot, ct_ptr, ct_row, ct_slot;
-  size_t tval, dvec, mean, U, Z, F, S, Q, W, aux1, aux2, aux3, red, tiles, tinv, status;
+  size_t tval, dvec, mean, U, Z, F, S, Q, P, W, aux1, aux2, aux3, dbar, red, tiles, tinv, status;
   size_t total;
 };
 
@@ -65,6 +65,7 @@ struct enkfmc_plan {
   std::vector<int32_t> csc_row, csc_nz;         // block-local row i and entry (relative to nz0) of T_iq
   std::vector<int32_t> interior_src;            // n: fit row that maps back onto each component
   std::vector<int32_t> bobs_o, bobs_row;        // per block observation list
+  std::vector<int32_t> bobs_fit;                // fit row of each block observation
   std::vector<int64_t> g2f_ptr;                 // n + 1: fit rows holding each component, sub-domain order
   std::vector<int32_t> g2f;
   std::vector<int64_t> o2b_ptr;                 // m + 1: block-observation entries of each observation
@@ -86,6 +87,7 @@ struct enkfmc_plan {
   int32_t fitted = 0, analyzed = 0;
   double fit_ridge = 0.0;
   const void *fit_xb = nullptr;
+  const void *an_y = nullptr, *an_r = nullptr;  // Y and r_diag of the last analysis
   // optional per-phase timing with HIP events on the call's stream
   int32_t timing = 0;
   void *ev[64] = {};
