@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-subdomains", type=int, default=6)
+    ap.add_argument("--adjoint-steps", type=int, default=3,
+                    help="also time fit + analyze + enkfmc_analyze_backward this many times (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (HBM counter calibration)")
     args = ap.parse_args()
@@ -136,6 +138,32 @@ def main():
         pdt, pph, _ = timed("plain", args.plain_steps, 1)
         plain = {"ms_per_step": pdt * 1e3, "value": prob.n / pdt, "phases_ms": pph}
         log(f"plain: {pdt * 1e3:.2f} ms/step; phases(ms) " + ", ".join(f"{k}={v:.3f}" for k, v in pph.items() if v > 0))
+        Xa = step(args.mode)
+
+    adjoint = None
+    if args.adjoint_steps > 0 and args.mode == "batched":
+        G = torch.as_tensor(np.random.default_rng(1).standard_normal((prob.n, prob.N))).cuda()
+        step(args.mode)
+        plan.backward(Xb, G)
+        plan.set_timing(True)
+        acc = {}
+        tb = 0.0
+        for _ in range(args.adjoint_steps):
+            step(args.mode)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            plan.backward(Xb, G)
+            torch.cuda.synchronize()
+            tb += time.perf_counter() - t
+            for k, v in plan.timing().items():
+                if k.startswith("adj") or k == "backward":
+                    acc[k] = acc.get(k, 0.0) + v
+        plan.set_timing(False)
+        adjoint = {"ms_backward": tb / args.adjoint_steps * 1e3,
+                   "phases_ms": {k: v / args.adjoint_steps for k, v in acc.items()},
+                   "note": "enkfmc_analyze_backward after each fit + analyze; dL/dX_b, dL/dlog r, dL/dlam"}
+        log(f"adjoint: {adjoint['ms_backward']:.2f} ms; phases(ms) "
+            + ", ".join(f"{k}={v:.3f}" for k, v in adjoint["phases_ms"].items()))
         Xa = step(args.mode)
 
     counts = np.concatenate([plan.row_counts(k) for k in range(info["n_subdomains"])])
@@ -212,6 +240,7 @@ def main():
         "rel_err_mean_vs_oracle": rel,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
     if args.copy_probe_mib > 0:

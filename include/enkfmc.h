@@ -180,6 +180,10 @@ enum {
   ENKFMC_PH_BACKWARD = 9,  /* whole reverse pass                                   */
   ENKFMC_PH_TILES = 10,    /* dense 16x16 tiles of T and inverse diagonal tiles     */
   ENKFMC_PH_FIT_KFORM = 11, /* kernel-form regressions (p >= N) alone, within FIT  */
+  ENKFMC_PH_ADJ_SOLVE = 12, /* adjoint: W = A^-1 Zbar (within BACKWARD)            */
+  ENKFMC_PH_ADJ_FACTOR = 13, /* adjoint: Dbar, betabar (within BACKWARD)           */
+  ENKFMC_PH_ADJ_REGRESS = 14, /* adjoint of the regressions (within BACKWARD)      */
+  ENKFMC_PH_ADJ_GATHER = 15, /* adjoint: halo gathers, dlog r, dlam (within BACKWARD) */
   ENKFMC_PH_COUNT = 16
 };
 enkfmc_status enkfmc_set_timing(enkfmc_plan *p, int32_t enable);

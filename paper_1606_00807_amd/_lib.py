@@ -20,7 +20,8 @@ F32, F64 = 0, 1
 FIT_PLAIN, FIT_BATCHED = 0, 1
 SOLVE_DUAL = 0
 PHASES = ["anomaly", "fit", "dual_F", "dual_S", "dual_chol", "dual_Q", "dual_G", "sweep", "mapback", "backward",
-          "tiles", "fit_kform"]
+          "tiles", "fit_kform",
+          "adj_solve", "adj_factor", "adj_regress", "adj_gather"]
 
 
 class Geometry(ctypes.Structure):

@@ -504,6 +504,7 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   const unsigned ct = (unsigned)((N + 15) / 16);
   phase_begin(p, ENKFMC_PH_BACKWARD, s);
   double *V = d.aux1;
+  phase_begin(p, ENKFMC_PH_ADJ_SOLVE, s);
   hipLaunchKernelGGL(k_adj_bwd_sweep, dim3(nb, ct), dim3(64), 0, s, d.blocks, d.ct_ptr, d.ct_row, d.ct_slot,
                      d.fit_glob, d.interior_src, d.tiles, d.tinv, dXa, N, V);
   if (p->max_bm > 0) {
@@ -512,21 +513,28 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   }
   hipError_t e = launch_fwd_sweep(p, d, d.P, V, d.W, s);
   if (e != hipSuccess) return e;
+  phase_end(p, ENKFMC_PH_ADJ_SOLVE, s);
   const unsigned gr = (unsigned)((p->n_fit + 3) / 4);
+  phase_begin(p, ENKFMC_PH_ADJ_FACTOR, s);
   hipLaunchKernelGGL(k_adj_factor_bar, dim3(gr), dim3(256), 0, s, d.blocks, d.fit_blk, d.row_ptr, d.col, d.tval,
                      d.dvec, d.Z, d.W, p->n_fit, N, d.dbar, d.aux3);
+  phase_end(p, ENKFMC_PH_ADJ_FACTOR, s);
   const size_t lds = adj_regress_lds(p);
   e = hipFuncSetAttribute((const void *)k_adj_regress, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  phase_begin(p, ENKFMC_PH_ADJ_REGRESS, s);
   hipLaunchKernelGGL(k_adj_regress, dim3((unsigned)p->n_fit), dim3(256), lds, s, d.blocks, d.fit_glob, d.fit_blk,
                      d.row_ptr, d.col, d.U, p->ldu, N, p->max_p, lam, d.tval, d.dbar, d.aux3, d.aux1, d.aux2, d.red,
                      d.status);
+  phase_end(p, ENKFMC_PH_ADJ_REGRESS, s);
+  phase_begin(p, ENKFMC_PH_ADJ_GATHER, s);
   hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)((p->n + 3) / 4)), dim3(256), 0, s, d.blocks, d.fit_blk, d.g2f_ptr,
                      d.g2f, d.csc_ptr, d.csc_row, d.csc_nz, d.tval, d.aux3, d.aux1, d.aux2, dXa, p->n, N, dXb);
   if (p->m > 0)
     hipLaunchKernelGGL(k_adj_obs<TX>, dim3((unsigned)((p->m + 3) / 4)), dim3(256), 0, s, d.o2b_ptr, d.o2b,
                        d.bobs_fit, d.fit_glob, d.Z, d.W, Y, Xb, ld, r_diag, p->m, N, dXb, dlogR);
   hipLaunchKernelGGL(k_adj_lambda, dim3(1), dim3(256), 0, s, d.red, p->n_fit, dridge);
+  phase_end(p, ENKFMC_PH_ADJ_GATHER, s);
   phase_end(p, ENKFMC_PH_BACKWARD, s);
   return hipGetLastError();
 }
