@@ -136,8 +136,9 @@ enkfmc_status enkfmc_analyze(enkfmc_plan *p, const void *Xb, int32_t dtype, int6
  * (dev, m float64, overwritten) and dL/dridge (dev, 1 float64, overwritten).
  * Needs the immediately preceding enkfmc_fit + enkfmc_analyze on the same
  * inputs (same Xb, Y, r_diag, ridge), else ESTATE.  Recomputes each
- * regression's Gram and factor instead of storing them.  Sums over the
- * overlapping halos in a fixed order, so results are bitwise repeatable. */
+ * regression's Gram and factor instead of storing them, in the form (plain or
+ * batched) of the preceding fit.  Sums over the overlapping halos in a fixed
+ * order, so results are bitwise repeatable.  EUNSUPPORTED for N > 128. */
 enkfmc_status enkfmc_analyze_backward(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t ld, const double *Y,
                                       const double *r_diag, const double *dXa, double *dXb, double *dlogR,
                                       double *dridge, void *stream);

@@ -172,6 +172,7 @@ enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t 
   st = finish(p, s, "fit");
   if (st != ENKFMC_OK) return st;
   p->fitted = 1;
+  p->fit_mode = mode;
   p->fit_ridge = ridge;
   p->fit_xb = Xb;
   return ENKFMC_OK;

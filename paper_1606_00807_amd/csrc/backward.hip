@@ -519,13 +519,16 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   hipLaunchKernelGGL(k_adj_factor_bar, dim3(gr), dim3(256), 0, s, d.blocks, d.fit_blk, d.row_ptr, d.col, d.tval,
                      d.dvec, d.Z, d.W, p->n_fit, N, d.dbar, d.aux3);
   phase_end(p, ENKFMC_PH_ADJ_FACTOR, s);
-  const size_t lds = adj_regress_lds(p);
-  e = hipFuncSetAttribute((const void *)k_adj_regress, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
   phase_begin(p, ENKFMC_PH_ADJ_REGRESS, s);
-  hipLaunchKernelGGL(k_adj_regress, dim3((unsigned)p->n_fit), dim3(256), lds, s, d.blocks, d.fit_glob, d.fit_blk,
-                     d.row_ptr, d.col, d.U, p->ldu, N, p->max_p, lam, d.tval, d.dbar, d.aux3, d.aux1, d.aux2, d.red,
-                     d.status);
+  if (p->fit_mode == ENKFMC_FIT_PLAIN || launch_adj_regress_batched(p, d, lam, s) == hipErrorNotSupported) {
+    // sizes beyond the one-wavefront kernels: one workgroup per regression
+    const size_t lds = adj_regress_lds(p);
+    e = hipFuncSetAttribute((const void *)k_adj_regress, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_regress, dim3((unsigned)p->n_fit), dim3(256), lds, s, d.blocks, d.fit_glob, d.fit_blk,
+                       d.row_ptr, d.col, d.U, p->ldu, N, p->max_p, lam, d.tval, d.dbar, d.aux3, d.aux1, d.aux2,
+                       d.red, d.status);
+  }
   phase_end(p, ENKFMC_PH_ADJ_REGRESS, s);
   phase_begin(p, ENKFMC_PH_ADJ_GATHER, s);
   hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)((p->n + 3) / 4)), dim3(256), 0, s, d.blocks, d.fit_blk, d.g2f_ptr,

@@ -117,6 +117,7 @@ hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const
                             hipStream_t s);
 hipError_t launch_analysis_dual(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld,
                                 const double *Y, const double *r_diag, void *Xa, int32_t out_dtype, hipStream_t s);
+hipError_t launch_adj_regress_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
 hipError_t launch_backward(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, const double *Y,
                            const double *r_diag, double lam, const double *dXa, double *dXb, double *dlogR,
                            double *dridge, hipStream_t s);

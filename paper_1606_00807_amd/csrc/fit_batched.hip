@@ -22,6 +22,16 @@
 // Every (T, form) pair is its own kernel, launched over a precomputed bucket
 // of rows, so that each kernel carries only the registers its T needs.
 //
+// The same routine, instantiated with ADJ, is the adjoint of a regression
+// (reverse pass of the fit).  Given Dbar = dL/dd and betabar = dL/dbeta of row
+// i, with G = U_P U_P^T/(N-1) + lam I and eps = u - U_P^T beta:
+//   epsbar = 2 Dbar eps/(N-1),  b = betabar - U_P epsbar,  s = G^-1 b,
+//   dL/dlam += -s . beta,  g = U_P^T s,
+//   e1 = eps/(N-1),  e2 = -(g/(N-1) + epsbar).
+// The right-hand side b (p-form) or U_P^T b (kernel form, where
+// (U_P U_P^T + mu I)^-1 = [I - U_P (U_P^T U_P + mu I)^-1 U_P^T]/mu) is formed
+// before the Gram, and the same Gram, Cholesky and back substitution follow.
+//
 // Layout of a v_mfma_f64_16x16x4 accumulator (lane l = 16q + c, register r):
 // element (4r + q, c).  A operand: lane l holds A[c][q]; B operand: B[q][c].
 #include "device.h"
@@ -76,18 +86,107 @@ __device__ inline double rsqrt_nr(double x) {
 template <int T>
 __device__ __forceinline__ constexpr int tix(int I, int J) { return I * (I + 1) / 2 + J; }
 
+// Arrays of the adjoint pass.
+struct AdjIO {
+  const double *dbar;   // dL/dd per fit row
+  double *sb;           // per CSR entry: betabar on entry, s on exit
+  double *e1, *e2;      // n_fit x N
+  double *lam_row;      // per fit row: its share of dL/dlam
+};
+
+// Adjoint pre-pass of row r, before its Gram: eps from the stored
+// coefficients, epsbar, b = betabar - U_P epsbar, and the right-hand side
+// (b, or U_P^T b in the kernel form) in the bordering row.  Leaves e1 = eps/(N-1),
+// e2 = epsbar and sb = b in global memory for the post-pass.
 template <int T, bool KF>
+__device__ __forceinline__ void adj_rhs(const int lane, const int64_t r, const int p, const int N,
+                                        const double *__restrict__ U, const int ldu, const int uoff, WaveLds<T> &L,
+                                        const double *__restrict__ tval, const int64_t lo, const AdjIO &adj,
+                                        double (&augv)[T]) {
+  const int q = lane >> 4, c = lane & 15;
+  const double nm1 = (double)(N - 1);
+  const double Db = adj.dbar[r];
+  double *bl = L.tile;             // beta, then b (kMaxP entries)
+  double *el = L.tile + kMaxP;     // epsbar (16 * kMaxT entries)
+  for (int a = lane; a < kMaxP; a += 64) bl[a] = a < p ? -tval[lo + a] : 0.0;
+  wave_lds_sync();
+  // eps_k = u_k - sum_a beta_a U[P_a][k]: lane (q, c) takes member 16I + c and
+  // predecessors a = q mod 4; the partial sums are then added across q.
+#pragma unroll
+  for (int I = 0; I < kMaxT; ++I) {
+    if (16 * I >= N) break;
+    const int k = 16 * I + c;
+    double e = 0.0;
+    for (int a = q; a < p; a += 4) e = fma(bl[a], U[L.pidx[a] * ldu + k], e);
+    e += __shfl_xor(e, 16, 64);
+    e += __shfl_xor(e, 32, 64);
+    const bool ok = k < N;
+    const double eps = ok ? U[uoff + k] - e : 0.0;
+    const double eb = 2.0 * Db * eps / nm1;
+    if (q == 0) {
+      el[k] = eb;
+      if (ok) {
+        adj.e1[r * N + k] = eps / nm1;
+        adj.e2[r * N + k] = eb;
+      }
+    }
+  }
+  wave_lds_sync();
+  // b_a = betabar_a - sum_k U[P_a][k] epsbar_k: lane (q, c) takes predecessor
+  // 16g + c and members k = q mod 4.
+  const int TN = (N + 15) >> 4;
+  auto b_of = [&](int g, int &a) {
+    a = 16 * g + c;
+    const int off = L.pidx[a] * ldu + q;
+    double sm = 0.0;
+    for (int j = 0; j < 4 * TN; ++j) sm = fma(U[off + 4 * j], el[4 * j + q], sm);
+    sm += __shfl_xor(sm, 16, 64);
+    sm += __shfl_xor(sm, 32, 64);
+    const double b = a < p ? adj.sb[lo + a] - sm : 0.0;
+    if (q == 0 && a < p) adj.sb[lo + a] = b;
+    return b;
+  };
+  if constexpr (!KF) {
+#pragma unroll
+    for (int g = 0; g < T; ++g) {   // p <= 16 T
+      int a;
+      const double b = b_of(g, a);
+      augv[g] = (q == 0 && a < p) ? b : 0.0;
+    }
+  } else {
+    const int G = (p + 15) >> 4;
+    for (int g = 0; g < G; ++g) {
+      int a;
+      const double b = b_of(g, a);
+      if (q == 0) bl[a] = b;          // a >= p gives 0, keeping the padding zero
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int I = 0; I < T; ++I) {     // (U_P^T b)_k, members k = 16I + c
+      const int k = 16 * I + c;
+      double e = 0.0;
+      for (int a = q; a < p; a += 4) e = fma(bl[a], U[L.pidx[a] * ldu + k], e);
+      e += __shfl_xor(e, 16, 64);
+      e += __shfl_xor(e, 32, 64);
+      augv[I] = (q == 0 && k < N) ? e : 0.0;
+    }
+  }
+  wave_lds_sync();
+}
+
+template <int T, bool KF, bool ADJ = false>
 __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const int p, const int N, const double mu,
                                         const double *__restrict__ U, const int ldu, const int uoff, WaveLds<T> &L,
                                         double *__restrict__ tval, const int64_t lo, double *__restrict__ dvec,
-                                        int32_t *status) {
+                                        int32_t *status, const AdjIO &adj) {
   constexpr int NT = T * (T + 1) / 2;
   const int q = lane >> 4, c = lane & 15;
   const int m = KF ? N : p;
+  double augv[T];   // bordering row: element 16J + c at lane (q = 0, c)
+  if constexpr (ADJ) adj_rhs<T, KF>(lane, r, p, N, U, ldu, uoff, L, tval, lo, adj, augv);
   d4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-  double augv[T];   // bordering row: element 16J + c at lane (q = 0, c)
 
   // ---- 1. Gram (+ right-hand side) -----------------------------------------
   // pidx[k] for k >= p names the all-zero pad row of U, so padded fragments
@@ -117,11 +216,13 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
         for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fb[I], fb[J], acc[tix<T>(I, J)]);
     }
+    if constexpr (!ADJ) {
 #pragma unroll
-    for (int J = 0; J < T; ++J) {
-      const int idx = 16 * J + c;
-      const double v = U[uoff + idx];
-      augv[J] = (idx < N && q == 0) ? v : 0.0;
+      for (int J = 0; J < T; ++J) {
+        const int idx = 16 * J + c;
+        const double v = U[uoff + idx];
+        augv[J] = (idx < N && q == 0) ? v : 0.0;
+      }
     }
   } else {
     // lane (q, c) also sums u_k U[P_{16I+c}][k] over members k = q mod 4.
@@ -138,19 +239,28 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       double f[T];
 #pragma unroll
       for (int I = 0; I < T; ++I) f[I] = U[base[I] + 4 * ks];
-      const double uk = U[uoff + q + 4 * ks];
+      if constexpr (ADJ) {
 #pragma unroll
-      for (int I = 0; I < T; ++I) {
+        for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I], f[J], acc[tix<T>(I, J)]);
-        vp[I] = fma(f[I], uk, vp[I]);
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I], f[J], acc[tix<T>(I, J)]);
+      } else {
+        const double uk = U[uoff + q + 4 * ks];
+#pragma unroll
+        for (int I = 0; I < T; ++I) {
+#pragma unroll
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I], f[J], acc[tix<T>(I, J)]);
+          vp[I] = fma(f[I], uk, vp[I]);
+        }
       }
     }
+    if constexpr (!ADJ) {
 #pragma unroll
-    for (int I = 0; I < T; ++I) {
-      vp[I] += __shfl_xor(vp[I], 16, 64);
-      vp[I] += __shfl_xor(vp[I], 32, 64);
-      augv[I] = (16 * I + c < m && q == 0) ? vp[I] : 0.0;
+      for (int I = 0; I < T; ++I) {
+        vp[I] += __shfl_xor(vp[I], 16, 64);
+        vp[I] += __shfl_xor(vp[I], 32, 64);
+        augv[I] = (16 * I + c < m && q == 0) ? vp[I] : 0.0;
+      }
     }
   }
   // ridge on the diagonal, identity on the padding
@@ -288,6 +398,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     wave_lds_sync();
   }
 
+  if constexpr (!ADJ) {
   // ---- 5. coefficients and residual variance --------------------------------
   // x (= w or beta) is zero beyond m, so the padded terms below vanish.
   double ss = 0.0;
@@ -344,6 +455,58 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     dvec[r] = dd;
     if (!(dd > 0.0)) set_error(status, ENKFMC_ENONPOS_D, (int32_t)r);
   }
+  } else {
+    // ---- 5'. adjoint: s, dL/dlam, e2 ------------------------------------------
+    const double nm1 = (double)(N - 1);
+    double *sl = L.tile;     // s (kMaxP entries)
+    double ls = 0.0;
+    const int G = (p + 15) >> 4;
+    if (KF) {
+      // s_a = (N-1)/mu (b_a - sum_k U[P_a][k] x_k), lanes as for beta above
+      double wq[4 * T];
+#pragma unroll
+      for (int j = 0; j < 4 * T; ++j) wq[j] = y[4 * j + q];
+      for (int g = 0; g < G; ++g) {
+        const int a = 16 * g + c;
+        const int off = L.pidx[a] * ldu + q;
+        double b = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4 * T; ++j) b = fma(U[off + 4 * j], wq[j], b);
+        b += __shfl_xor(b, 16, 64);
+        b += __shfl_xor(b, 32, 64);
+        if (q == 0 && a < p) {
+          const double sv = (nm1 / mu) * (adj.sb[lo + a] - b);
+          sl[a] = sv;
+          adj.sb[lo + a] = sv;
+          ls = fma(sv, tval[lo + a], ls);
+        }
+      }
+    } else {
+      for (int g = 0; g < G; ++g) {
+        const int a = 16 * g + c;
+        if (q == 0 && a < p) {
+          const double sv = nm1 * y[a];
+          sl[a] = sv;
+          adj.sb[lo + a] = sv;
+          ls = fma(sv, tval[lo + a], ls);
+        }
+      }
+    }
+    wave_lds_sync();
+    // e2 = -(U_P^T s/(N-1) + epsbar), epsbar left in e2 by the pre-pass
+#pragma unroll
+    for (int I = 0; I < kMaxT; ++I) {
+      if (16 * I >= N) break;
+      const int k = 16 * I + c;
+      double e = 0.0;
+      for (int a = q; a < p; a += 4) e = fma(sl[a], U[L.pidx[a] * ldu + k], e);
+      e += __shfl_xor(e, 16, 64);
+      e += __shfl_xor(e, 32, 64);
+      if (q == 0 && k < N) adj.e2[r * N + k] = -(e / nm1 + adj.e2[r * N + k]);
+    }
+    ls = wave_sum(ls);
+    if (lane == 0) adj.lam_row[r] = ls;
+  }
 }
 
 // waves per SIMD each kernel is compiled for (register budget 512 / occupancy)
@@ -371,7 +534,50 @@ __global__ __launch_bounds__(256, occupancy_for(T, KF)) void k_fit_batched(
     if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
     return;
   }
-  fit_row<T, KF>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, dvec, status);
+  fit_row<T, KF>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, dvec, status, AdjIO{});
+}
+
+// Adjoint of the regressions of one bucket (same rows and shapes as the fit).
+// The adjoint carries the pre- and post-pass values too: one wave per SIMD less
+// for the larger kernel-form systems.
+constexpr int adj_occupancy_for(int T, bool KF) { return KF ? (T <= 2 ? 4 : (T == 3 ? 3 : 2)) : occupancy_for(T, KF); }
+
+template <int T, bool KF>
+__global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_batched(
+    const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
+    int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, double lam, double *__restrict__ tval,
+    AdjIO adj, int32_t *status) {
+  __shared__ WaveLds<T> lds[4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + wave;
+  if (idx >= nrows) return;
+  const int64_t r = rows[idx];
+  WaveLds<T> &L = lds[wave];
+  const Block B = blocks[fit_blk[r]];
+  const int64_t lo = row_ptr[r];
+  const int p = (int)(row_ptr[r + 1] - lo);
+  const int uoff = fit_glob[r] * ldu;
+  for (int k = lane; k < kMaxP + 8; k += 64) L.pidx[k] = k < p ? fit_glob[B.row0 + col[lo + k]] : zrow;
+  wave_lds_sync();
+  fit_row<T, KF, true>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, nullptr, status, adj);
+}
+
+// Adjoint of the regressions without predecessors (eps = u).
+__global__ __launch_bounds__(256) void k_adj_p0(const int32_t *__restrict__ fit_glob, const double *__restrict__ U,
+                                                int ldu, int N, const int32_t *__restrict__ rows, int64_t nrows,
+                                                AdjIO adj) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + wave;
+  if (idx >= nrows) return;
+  const int64_t r = rows[idx];
+  const double *u = U + (int64_t)fit_glob[r] * ldu;
+  const double nm1 = (double)(N - 1), Db = adj.dbar[r];
+  for (int cc = lane; cc < N; cc += 64) {
+    adj.e1[r * N + cc] = u[cc] / nm1;
+    adj.e2[r * N + cc] = -2.0 * Db * u[cc] / nm1;
+  }
+  if (lane == 0) adj.lam_row[r] = 0.0;
 }
 
 // Regressions without predecessors: d = u^T u / (N - 1).
@@ -431,6 +637,45 @@ hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStrea
     launch_bucket<5, false>(p, d, rows + bo[6], nk, lam, s);   // p >= N without ridge: ENOTSPD
   }
   phase_end(p, ENKFMC_PH_FIT, s);
+  return hipGetLastError();
+}
+
+
+template <int T, bool KF>
+static void launch_adj_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam,
+                              const AdjIO &adj, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_adj_regress_batched<T, KF>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d.blocks,
+                     d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam, d.tval, adj,
+                     d.status);
+}
+
+// Adjoint of every regression over the fit's buckets.  hipErrorNotSupported
+// when the sizes exceed this kernel (the caller then uses the plain form).
+hipError_t launch_adj_regress_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s) {
+  if (p->N > 16 * kMaxT || p->max_p > kMaxP) return hipErrorNotSupported;
+  const AdjIO adj{d.dbar, d.aux3, d.aux1, d.aux2, d.red};
+  const int32_t *rows = d.fit_rows;
+  const int64_t *bo = p->bucket_off;
+  if (bo[1] > bo[0])
+    hipLaunchKernelGGL(k_adj_p0, dim3((unsigned)((bo[1] - bo[0] + 3) / 4)), dim3(256), 0, s, d.fit_glob, d.U, p->ldu,
+                       p->N, rows + bo[0], bo[1] - bo[0], adj);
+  launch_adj_bucket<1, false>(p, d, rows + bo[1], bo[2] - bo[1], lam, adj, s);
+  launch_adj_bucket<2, false>(p, d, rows + bo[2], bo[3] - bo[2], lam, adj, s);
+  launch_adj_bucket<3, false>(p, d, rows + bo[3], bo[4] - bo[3], lam, adj, s);
+  launch_adj_bucket<4, false>(p, d, rows + bo[4], bo[5] - bo[4], lam, adj, s);
+  launch_adj_bucket<5, false>(p, d, rows + bo[5], bo[6] - bo[5], lam, adj, s);
+  const int64_t nk = bo[7] - bo[6];
+  if (nk > 0) {
+    if (!(lam > 0.0)) return hipErrorInvalidValue;   // the fit rejects p >= N - 1 without ridge
+    switch ((p->N + 15) / 16) {
+      case 1: launch_adj_bucket<1, true>(p, d, rows + bo[6], nk, lam, adj, s); break;
+      case 2: launch_adj_bucket<2, true>(p, d, rows + bo[6], nk, lam, adj, s); break;
+      case 3: launch_adj_bucket<3, true>(p, d, rows + bo[6], nk, lam, adj, s); break;
+      case 4: launch_adj_bucket<4, true>(p, d, rows + bo[6], nk, lam, adj, s); break;
+      default: launch_adj_bucket<5, true>(p, d, rows + bo[6], nk, lam, adj, s); break;
+    }
+  }
   return hipGetLastError();
 }
 

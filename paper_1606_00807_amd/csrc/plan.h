@@ -85,6 +85,7 @@ struct enkfmc_plan {
   size_t ws_bytes = 0;
   int32_t device = -1;
   int32_t fitted = 0, analyzed = 0;
+  int32_t fit_mode = 0;            // enkfmc_fit_mode of the last fit (the reverse pass uses the same form)
   double fit_ridge = 0.0;
   const void *fit_xb = nullptr;
   const void *an_y = nullptr, *an_r = nullptr;  // Y and r_diag of the last analysis
