@@ -23,11 +23,16 @@
 namespace enkfmc {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 __device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
 // Dense tiles T_RC (row-major) of row tile R, and the inverse of T_RR.
-// One 64-lane workgroup per (block, row tile).
+// One wavefront per (block, row tile).  Each lane fills whole tile rows: for
+// (row i, column tile C) it finds the entries of row i with columns in
+// [16C, 16C + 16) (contiguous, as a row's predecessors are ascending) and writes
+// the 16 values, zeros included.  The diagonal tile also goes to LDS, where 16
+// lanes invert it.
 __global__ __launch_bounds__(64) void k_build_tiles(const Block *__restrict__ blocks,
                                                     const int64_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ col, const double *__restrict__ tval,
@@ -35,7 +40,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(const Block *__restrict__ bl
                                                     const int32_t *__restrict__ rt_col,
                                                     const int32_t *__restrict__ rt_slot, double *__restrict__ tiles,
                                                     double *__restrict__ tinv) {
-  extern __shared__ double sm[];
+  __shared__ double diag[256];
   const Block B = blocks[blockIdx.x];
   const int R = blockIdx.y;
   if (R >= B.nrt) return;
@@ -43,34 +48,35 @@ __global__ __launch_bounds__(64) void k_build_tiles(const Block *__restrict__ bl
   const int64_t rt = B.rt0 + R;
   const int64_t t0 = rt_ptr[rt];
   const int nt = (int)(rt_ptr[rt + 1] - t0);
-  double *diag = sm + (size_t)nt * 256;
-  int *cols = (int *)(diag + 256);
-  int64_t *rp = (int64_t *)(cols + nt + 1 + ((nt + 1) & 1));
-  for (int e = lane; e < (nt + 1) * 256; e += 64) sm[e] = 0.0;
-  for (int t = lane; t < nt; t += 64) cols[t] = rt_col[t0 + t];
-  const int i0 = 16 * R, i1 = min(B.n, 16 * R + 16);
-  for (int i = lane; i <= i1 - i0; i += 64) rp[i] = row_ptr[B.row0 + i0 + i];
-  __syncthreads();
-  const int64_t k0 = rp[0], k1 = rp[i1 - i0];
-  for (int64_t k = k0 + lane; k < k1; k += 64) {
-    int i = 0;
-    while (rp[i + 1] <= k) ++i;
-    const int qcol = col[k];
-    const int C = qcol >> 4;
-    const int e = i * 16 + (qcol & 15);
-    if (C == R) {
-      diag[e] = tval[k];
-    } else {
-      int t = 0;
-      while (t < nt && cols[t] != C) ++t;
-      if (t < nt) sm[t * 256 + e] = tval[k];
+  for (int pr = lane; pr < 16 * (nt + 1); pr += 64) {
+    const int i = pr & 15, t = pr >> 4;          // t == nt: the diagonal tile
+    const int C = t < nt ? rt_col[t0 + t] : R;
+    const int row = 16 * R + i;
+    double v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = 0.0;
+    if (row < B.n) {
+      const int64_t ka = row_ptr[B.row0 + row], kb = row_ptr[B.row0 + row + 1];
+      int64_t lo = ka, hi = kb;                  // first entry with col >= 16C
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < 16 * C) lo = mid + 1;
+        else hi = mid;
+      }
+      int64_t k = lo;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (k < kb && col[k] == 16 * C + j) {
+          v[j] = tval[k];
+          ++k;
+        }
+      }
     }
+    double *dst = (t < nt ? tiles + (int64_t)rt_slot[t0 + t] * 256 : diag) + i * 16;
+#pragma unroll
+    for (int j = 0; j < 16; j += 2) *(d2 *)(dst + j) = d2{v[j], v[j + 1]};
   }
   __syncthreads();
-  for (int t = 0; t < nt; ++t) {
-    double *dst = tiles + (int64_t)rt_slot[t0 + t] * 256;
-    for (int e = lane; e < 256; e += 64) dst[e] = sm[t * 256 + e];
-  }
   if (lane < 16) {
     // column `lane` of (I + L)^-1 by forward substitution
     const int j = lane;
@@ -225,44 +231,66 @@ __global__ __launch_bounds__(64) void k_dual_Q(const Block *__restrict__ blocks,
   for (int a = m; a < lds; ++a) q[(int64_t)a * N + c] = 0.0;
 }
 
-// Z = T^-1 (D (F Q)), forward over row tiles; one wavefront per (block, 16 member columns).
-// With V (n_fit x N) given it computes Z = T^-1 (D (V - F Q)) instead (the
-// adjoint solve reuses it).
+// G = D (F Q) of row tile R (or D (V - F Q) with V given), written into the
+// output rows that the forward sweep then solves in place.  One wavefront per
+// (block, row tile); it loops over the 16-member column tiles.
+__global__ __launch_bounds__(64) void k_dual_G(const Block *__restrict__ blocks, const double *__restrict__ F,
+                                               const double *__restrict__ Q, const double *__restrict__ dvec,
+                                               const double *__restrict__ V, int N, double *__restrict__ G) {
+  const Block B = blocks[blockIdx.x];
+  const int R = blockIdx.y;
+  if (R >= B.nrt) return;
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int ldf = B.ldf;
+  const double *Fr = F + B.F0 + (int64_t)(16 * R + c) * ldf + q;
+  const double *Qb = Q + B.Q0;
+  double dd[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * R + 4 * r + q;
+    dd[r] = row < B.n ? dvec[B.row0 + row] : 0.0;
+  }
+  for (int cc = 0; 16 * cc < N; ++cc) {
+    const int colj = 16 * cc + c;
+    const bool colok = colj < N;
+    const int coll = colok ? colj : 0;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    for (int ks = 0; ks < (ldf >> 2); ++ks) {
+      const double bq = Qb[(int64_t)(4 * ks + q) * N + coll];
+      acc = mfma64(Fr[4 * ks], colok ? bq : 0.0, acc);
+    }
+    if (!colok) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * R + 4 * r + q;
+      if (row < B.n) {
+        const int64_t o = (B.row0 + row) * N + colj;
+        G[o] = V ? dd[r] * (V[o] - acc[r]) : dd[r] * acc[r];
+      }
+    }
+  }
+}
+
+// Z = T^-1 G in place (G from k_dual_G), forward over row tiles; one wavefront
+// per (block, 16 member columns).  Row tile R: Z_R = T_RR^-1 (G_R - sum_C T_RC Z_C).
 __global__ __launch_bounds__(64) void k_fwd_sweep(const Block *__restrict__ blocks, const int64_t *__restrict__ rt_ptr,
                                                   const int32_t *__restrict__ rt_col,
                                                   const int32_t *__restrict__ rt_slot,
                                                   const double *__restrict__ tiles, const double *__restrict__ tinv,
-                                                  const double *__restrict__ F, const double *__restrict__ Q,
-                                                  const double *__restrict__ dvec, const double *__restrict__ V, int N,
-                                                  double *__restrict__ Z) {
+                                                  int N, double *__restrict__ Z) {
   const Block B = blocks[blockIdx.x];
   const int cc = blockIdx.y;
   const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
   const int colj = 16 * cc + c;
   const bool colok = colj < N;
   const int coll = colok ? colj : 0;
-  const int ldf = B.ldf;
-  const double *Fb = F + B.F0;
-  const double *Qb = Q + B.Q0;
   double *Zb = Z + B.row0 * N;
   for (int R = 0; R < B.nrt; ++R) {
-    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-    const double *Fr = Fb + (int64_t)(16 * R + c) * ldf + q;
-    for (int ks = 0; ks < (ldf >> 2); ++ks) {
-      const double bq = Qb[(int64_t)(4 * ks + q) * N + coll];
-      acc = mfma64(Fr[4 * ks], colok ? bq : 0.0, acc);
-    }
+    d4 acc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * R + 4 * r + q;
-      const bool in = row < B.n;
-      const double dd = in ? dvec[B.row0 + row] : 0.0;
-      if (V) {
-        const double v = in && colok ? V[(B.row0 + row) * N + colj] : 0.0;
-        acc[r] = dd * (v - acc[r]);
-      } else {
-        acc[r] *= dd;
-      }
+      acc[r] = (row < B.n && colok) ? Zb[(int64_t)row * N + colj] : 0.0;
     }
     const int64_t s0 = rt_ptr[B.rt0 + R], s1 = rt_ptr[B.rt0 + R + 1];
     for (int64_t t = s0; t < s1; ++t) {
@@ -301,11 +329,6 @@ __global__ __launch_bounds__(256) void k_mapback(const TX *__restrict__ Xb, int6
   Xa[idx] = (TO)((double)Xb[g * ld + c] + Z[(int64_t)src[g] * N + c]);
 }
 
-size_t build_tiles_lds(const enkfmc_plan *p) {
-  const int nt = p->max_rt_tiles;
-  return (size_t)(nt + 1) * 256 * 8 + (size_t)(nt + 2) * 4 + 17 * 8 + 16;
-}
-
 int max_block_tiles(const enkfmc_plan *p) {
   int mx = 0;
   for (const Block &B : p->blocks) mx = B.nrt > mx ? B.nrt : mx;
@@ -313,13 +336,24 @@ int max_block_tiles(const enkfmc_plan *p) {
 }
 
 hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s) {
-  const size_t lds = build_tiles_lds(p);
-  hipError_t e = hipFuncSetAttribute((const void *)k_build_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
   phase_begin(p, ENKFMC_PH_TILES, s);
-  hipLaunchKernelGGL(k_build_tiles, dim3((unsigned)p->blocks.size(), (unsigned)max_block_tiles(p)), dim3(64), lds, s,
+  hipLaunchKernelGGL(k_build_tiles, dim3((unsigned)p->blocks.size(), (unsigned)max_block_tiles(p)), dim3(64), 0, s,
                      d.blocks, d.row_ptr, d.col, d.tval, d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tinv);
   phase_end(p, ENKFMC_PH_TILES, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const double *V, double *out,
+                            hipStream_t s) {
+  const unsigned nb = (unsigned)p->blocks.size();
+  phase_begin(p, ENKFMC_PH_DUAL_G, s);
+  hipLaunchKernelGGL(k_dual_G, dim3(nb, (unsigned)max_block_tiles(p)), dim3(64), 0, s, d.blocks, d.F, Q, d.dvec, V,
+                     p->N, out);
+  phase_end(p, ENKFMC_PH_DUAL_G, s);
+  phase_begin(p, ENKFMC_PH_SWEEP, s);
+  hipLaunchKernelGGL(k_fwd_sweep, dim3(nb, (p->N + 15) / 16), dim3(64), 0, s, d.blocks, d.rt_ptr, d.rt_col, d.rt_slot,
+                     d.tiles, d.tinv, p->N, out);
+  phase_end(p, ENKFMC_PH_SWEEP, s);
   return hipGetLastError();
 }
 
@@ -346,10 +380,8 @@ static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
                        d.fit_glob, d.S, Y, Xb, ld, N, d.Q);
     phase_end(p, ENKFMC_PH_DUAL_Q, s);
   }
-  phase_begin(p, ENKFMC_PH_SWEEP, s);
-  hipLaunchKernelGGL(k_fwd_sweep, dim3(nb, (N + 15) / 16), dim3(64), 0, s, d.blocks, d.rt_ptr, d.rt_col, d.rt_slot,
-                     d.tiles, d.tinv, d.F, d.Q, d.dvec, (const double *)nullptr, N, d.Z);
-  phase_end(p, ENKFMC_PH_SWEEP, s);
+  hipError_t e = launch_fwd_sweep(p, d, d.Q, nullptr, d.Z, s);
+  if (e != hipSuccess) return e;
   const int64_t tot = p->n * N;
   const dim3 g((unsigned)((tot + 255) / 256));
   phase_begin(p, ENKFMC_PH_MAPBACK, s);
@@ -362,12 +394,6 @@ static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   return hipGetLastError();
 }
 
-hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const double *V, double *out,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_fwd_sweep, dim3((unsigned)p->blocks.size(), (p->N + 15) / 16), dim3(64), 0, s, d.blocks,
-                     d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tinv, d.F, Q, d.dvec, V, p->N, out);
-  return hipGetLastError();
-}
 
 hipError_t launch_analysis_dual(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld,
                                 const double *Y, const double *r_diag, void *Xa, int32_t out_dtype, hipStream_t s) {
