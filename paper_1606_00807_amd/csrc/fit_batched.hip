@@ -132,35 +132,39 @@ __device__ __forceinline__ void adj_rhs(const int lane, const int64_t r, const i
     }
   }
   wave_lds_sync();
-  // b_a = betabar_a - sum_k U[P_a][k] epsbar_k: lane (q, c) takes predecessor
-  // 16g + c and members k = q mod 4.
+  // b_a = betabar_a - sum_k U[P_a][k] epsbar_k: lane (q, c) loads members
+  // 16I + c of predecessor 4ks + q and the 16 lanes of each quarter add up.
   const int TN = (N + 15) >> 4;
-  auto b_of = [&](int g, int &a) {
-    a = 16 * g + c;
-    const int off = L.pidx[a] * ldu + q;
+  double ev[kMaxT];
+#pragma unroll
+  for (int I = 0; I < kMaxT; ++I) ev[I] = I < TN ? el[16 * I + c] : 0.0;
+  const int ksteps = (p + 3) >> 2;
+  for (int ks = 0; ks < ksteps; ++ks) {
+    const int a = 4 * ks + q;
+    const int off = L.pidx[a] * ldu + c;
     double sm = 0.0;
-    for (int j = 0; j < 4 * TN; ++j) sm = fma(U[off + 4 * j], el[4 * j + q], sm);
-    sm += __shfl_xor(sm, 16, 64);
-    sm += __shfl_xor(sm, 32, 64);
-    const double b = a < p ? adj.sb[lo + a] - sm : 0.0;
-    if (q == 0 && a < p) adj.sb[lo + a] = b;
-    return b;
-  };
+#pragma unroll
+    for (int I = 0; I < kMaxT; ++I)
+      if (I < TN) sm = fma(U[off + 16 * I], ev[I], sm);
+    sm += __shfl_xor(sm, 8, 16);
+    sm += __shfl_xor(sm, 4, 16);
+    sm += __shfl_xor(sm, 2, 16);
+    sm += __shfl_xor(sm, 1, 16);
+    if (c == 0 && a < p) {
+      const double b = adj.sb[lo + a] - sm;
+      adj.sb[lo + a] = b;
+      bl[a] = b;
+    }
+  }
+  // entries a >= p of bl still hold the zero padding written above
+  wave_lds_sync();
   if constexpr (!KF) {
 #pragma unroll
     for (int g = 0; g < T; ++g) {   // p <= 16 T
-      int a;
-      const double b = b_of(g, a);
-      augv[g] = (q == 0 && a < p) ? b : 0.0;
+      const int a = 16 * g + c;
+      augv[g] = (q == 0 && a < p) ? bl[a] : 0.0;
     }
   } else {
-    const int G = (p + 15) >> 4;
-    for (int g = 0; g < G; ++g) {
-      int a;
-      const double b = b_of(g, a);
-      if (q == 0) bl[a] = b;          // a >= p gives 0, keeping the padding zero
-    }
-    wave_lds_sync();
 #pragma unroll
     for (int I = 0; I < T; ++I) {     // (U_P^T b)_k, members k = 16I + c
       const int k = 16 * I + c;
@@ -403,21 +407,24 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   // x (= w or beta) is zero beyond m, so the padded terms below vanish.
   double ss = 0.0;
   if (KF) {
-    // beta_a = sum_k U[P_a][k] w_k: lane (q, c) takes predecessor 16g + c and
-    // members k = q mod 4; the four partial sums are then added across q.
-    double wq[4 * T];
+    // beta_a = sum_k U[P_a][k] w_k: lane (q, c) loads members 16I + c of
+    // predecessor 4ks + q (the Gram's coalesced fragments); the 16 lanes of
+    // each quarter then add their partial sums.
+    double wv[T];
 #pragma unroll
-    for (int j = 0; j < 4 * T; ++j) wq[j] = y[4 * j + q];
-    const int G = (p + 15) >> 4;
-    for (int g = 0; g < G; ++g) {
-      const int a = 16 * g + c;
-      const int off = L.pidx[a] * ldu + q;
+    for (int I = 0; I < T; ++I) wv[I] = y[16 * I + c];
+    const int ksteps = (p + 3) >> 2;
+    for (int ks = 0; ks < ksteps; ++ks) {
+      const int a = 4 * ks + q;
+      const int off = L.pidx[a] * ldu + c;
       double b = 0.0;
 #pragma unroll
-      for (int j = 0; j < 4 * T; ++j) b = fma(U[off + 4 * j], wq[j], b);
-      b += __shfl_xor(b, 16, 64);
-      b += __shfl_xor(b, 32, 64);
-      if (q == 0 && a < p) tval[lo + a] = -b;
+      for (int I = 0; I < T; ++I) b = fma(U[off + 16 * I], wv[I], b);
+      b += __shfl_xor(b, 8, 16);
+      b += __shfl_xor(b, 4, 16);
+      b += __shfl_xor(b, 2, 16);
+      b += __shfl_xor(b, 1, 16);
+      if (c == 0 && a < p) tval[lo + a] = -b;
     }
     if (q == 0) {
 #pragma unroll
@@ -460,21 +467,23 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     const double nm1 = (double)(N - 1);
     double *sl = L.tile;     // s (kMaxP entries)
     double ls = 0.0;
-    const int G = (p + 15) >> 4;
     if (KF) {
       // s_a = (N-1)/mu (b_a - sum_k U[P_a][k] x_k), lanes as for beta above
-      double wq[4 * T];
+      double wv[T];
 #pragma unroll
-      for (int j = 0; j < 4 * T; ++j) wq[j] = y[4 * j + q];
-      for (int g = 0; g < G; ++g) {
-        const int a = 16 * g + c;
-        const int off = L.pidx[a] * ldu + q;
+      for (int I = 0; I < T; ++I) wv[I] = y[16 * I + c];
+      const int ksteps = (p + 3) >> 2;
+      for (int ks = 0; ks < ksteps; ++ks) {
+        const int a = 4 * ks + q;
+        const int off = L.pidx[a] * ldu + c;
         double b = 0.0;
 #pragma unroll
-        for (int j = 0; j < 4 * T; ++j) b = fma(U[off + 4 * j], wq[j], b);
-        b += __shfl_xor(b, 16, 64);
-        b += __shfl_xor(b, 32, 64);
-        if (q == 0 && a < p) {
+        for (int I = 0; I < T; ++I) b = fma(U[off + 16 * I], wv[I], b);
+        b += __shfl_xor(b, 8, 16);
+        b += __shfl_xor(b, 4, 16);
+        b += __shfl_xor(b, 2, 16);
+        b += __shfl_xor(b, 1, 16);
+        if (c == 0 && a < p) {
           const double sv = (nm1 / mu) * (adj.sb[lo + a] - b);
           sl[a] = sv;
           adj.sb[lo + a] = sv;
@@ -482,9 +491,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         }
       }
     } else {
-      for (int g = 0; g < G; ++g) {
-        const int a = 16 * g + c;
-        if (q == 0 && a < p) {
+      // same lane per entry as the pre-pass, which stored b there
+      for (int ks = 0; 4 * ks < p; ++ks) {
+        const int a = 4 * ks + q;
+        if (c == 0 && a < p) {
           const double sv = nm1 * y[a];
           sl[a] = sv;
           adj.sb[lo + a] = sv;
