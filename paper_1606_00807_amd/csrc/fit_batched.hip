@@ -283,6 +283,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
   for (int J = 0; J < T; ++J) {
     // pivot of the panel's first column (after the trailing updates)
+    // Columns stay unscaled while the panel is eliminated: column k is
+    // broadcast as is and the update uses a[i][k] a[j][k] / piv_k.  At the end
+    // of the panel each column c is scaled once by its 1/L_cc, which also turns
+    // its final pivot on the diagonal into L_cc.
     double piv = readlane_d(acc[tix<T>(J, J)][0], 0);
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
@@ -291,44 +295,43 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         return;
       }
       const double inv = rsqrt_nr(piv);
-      const double lkk = piv * inv;
       if (lane == 0) L.dinv[16 * J + kk] = inv;
       if (c == kk) {
 #pragma unroll
-        for (int I = J; I < T; ++I) {
-          d4 v = acc[tix<T>(I, J)];
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) v[rr] = (I == J && 4 * rr + q == kk) ? lkk : v[rr] * inv;
-          acc[tix<T>(I, J)] = v;
-          *(d4 *)&L.col[16 * I + 4 * q] = v;
-        }
+        for (int I = J; I < T; ++I) *(d4 *)&L.col[16 * I + 4 * q] = acc[tix<T>(I, J)];
         if (q == 0) {
           augv[J] *= inv;
           L.col[16 * T] = augv[J];
         }
       }
-      // lookahead: the next pivot only needs L[k+1][k] and the not yet updated
-      // A[k+1][k+1]; computing it here takes the reciprocal square root off the
-      // path through the column broadcast (same fma as the update below)
+      // lookahead: the next pivot only needs a[k+1][k] and the not yet updated
+      // a[k+1][k+1]; computing it here takes the reciprocal square root off the
+      // path through the column broadcast
       if (kk + 1 < 16) {
         const int q1 = (kk + 1) & 3, r1 = (kk + 1) >> 2;
-        const double lnext = readlane_d(acc[tix<T>(J, J)][r1], 16 * q1 + kk);
+        const double lnext = readlane_d(acc[tix<T>(J, J)][r1], 16 * q1 + kk) * inv;
         const double anext = readlane_d(acc[tix<T>(J, J)][r1], 16 * q1 + kk + 1);
         piv = fma(-lnext, lnext, anext);
       }
       wave_lds_sync();
       const double colv = L.col[16 * J + 4 * (c & 3) + (c >> 2)];
-      const double cv = c > kk ? colv : 0.0;
+      const double cv1 = c > kk ? colv * inv : 0.0;   // L[16J + c][k]
+      const double cv2 = cv1 * inv;
 #pragma unroll
       for (int I = J; I < T; ++I) {
         const d4 rowv = *(const d4 *)&L.col[16 * I + 4 * q];
         d4 v = acc[tix<T>(I, J)];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) v[rr] = fma(-rowv[rr], cv, v[rr]);
+        for (int rr = 0; rr < 4; ++rr) v[rr] = fma(-rowv[rr], cv2, v[rr]);
         acc[tix<T>(I, J)] = v;
       }
-      augv[J] = fma(-L.col[16 * T], cv, augv[J]);
+      augv[J] = fma(-L.col[16 * T], cv1, augv[J]);
       wave_lds_sync();
+    }
+    {
+      const double myinv = L.dinv[16 * J + c];
+#pragma unroll
+      for (int I = J; I < T; ++I) acc[tix<T>(I, J)] *= myinv;
     }
     if (J + 1 < T) {
       // transpose the panel tiles below the diagonal into LDS (row-major, padded);
