@@ -132,7 +132,8 @@ __global__ __launch_bounds__(64) void k_bwd_sweep(const Block *__restrict__ bloc
   }
 }
 
-// S = R + F^T D F (lower tiles, stride ldf); one wavefront per (block, tile column J).
+// S = R + F^T D F (lower tiles, stride ldf); one wavefront per (block, tile
+// column J, chunk of up to 8 tile rows I >= J).
 __global__ __launch_bounds__(64) void k_dual_S(const Block *__restrict__ blocks, const int32_t *__restrict__ bobs_o,
                                                const double *__restrict__ F, const double *__restrict__ dvec,
                                                const double *__restrict__ r_diag, double *__restrict__ S) {
@@ -140,7 +141,8 @@ __global__ __launch_bounds__(64) void k_dual_S(const Block *__restrict__ blocks,
   const Block B = blocks[blockIdx.x];
   const int J = blockIdx.y;
   const int TJ = B.ldf >> 4;
-  if (J >= TJ) return;
+  const int I0 = J + kMaxTiles * (int)blockIdx.z;
+  if (J >= TJ || I0 >= TJ) return;
   const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
   const int ldf = B.ldf;
   const double *Fb = F + B.F0;
@@ -154,17 +156,18 @@ __global__ __launch_bounds__(64) void k_dual_S(const Block *__restrict__ blocks,
     const double *Fk = Fb + (int64_t)k * ldf + c;
     const double b = dk * Fk[16 * J];
 #pragma unroll
-    for (int I = 0; I < kMaxTiles; ++I)
-      if (I >= J && I < TJ) acc[I] = mfma64(Fk[16 * I], b, acc[I]);
+    for (int i = 0; i < kMaxTiles; ++i)
+      if (I0 + i < TJ) acc[i] = mfma64(Fk[16 * (I0 + i)], b, acc[i]);
   }
   double *Sb = S + B.S0;
 #pragma unroll
-  for (int I = 0; I < kMaxTiles; ++I) {
-    if (I >= J && I < TJ) {
+  for (int i = 0; i < kMaxTiles; ++i) {
+    const int I = I0 + i;
+    if (I < TJ) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a = 16 * I + 4 * r + q, bb = 16 * J + c;
-        double v = acc[I][r];
+        double v = acc[i][r];
         if (a == bb) v = a < B.m ? v + r_diag[bobs_o[B.obs0 + a]] : 1.0;
         Sb[(int64_t)a * ldf + bb] = v;
       }
@@ -363,14 +366,13 @@ static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   const unsigned nb = (unsigned)p->blocks.size();
   const int N = p->N;
   const unsigned oc = (unsigned)((p->max_bm + 15) / 16);
-  if (oc > 8) return hipErrorInvalidValue;   // k_dual_S keeps at most 8 tile rows
   if (p->max_bm > 0) {
     phase_begin(p, ENKFMC_PH_DUAL_F, s);
     hipLaunchKernelGGL(k_bwd_sweep, dim3(nb, oc), dim3(64), 0, s, d.blocks, d.ct_ptr, d.ct_row, d.ct_slot, d.bobs_row,
                        d.tiles, d.tinv, d.F);
     phase_end(p, ENKFMC_PH_DUAL_F, s);
     phase_begin(p, ENKFMC_PH_DUAL_S, s);
-    hipLaunchKernelGGL(k_dual_S, dim3(nb, oc), dim3(64), 0, s, d.blocks, d.bobs_o, d.F, d.dvec, r_diag, d.S);
+    hipLaunchKernelGGL(k_dual_S, dim3(nb, oc, (oc + 7) / 8), dim3(64), 0, s, d.blocks, d.bobs_o, d.F, d.dvec, r_diag, d.S);
     phase_end(p, ENKFMC_PH_DUAL_S, s);
     phase_begin(p, ENKFMC_PH_DUAL_CHOL, s);
     hipLaunchKernelGGL(k_dual_chol, dim3(nb), dim3(256), 0, s, d.blocks, d.S, d.status);

@@ -185,8 +185,6 @@ enkfmc_status enkfmc_analyze(enkfmc_plan *p, const void *Xb, int32_t dtype, int6
   if (out_dtype != ENKFMC_F32 && out_dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "analyze: bad out_dtype");
   if (ld < p->N) return fail(ENKFMC_EINVAL, "analyze: ld < N");
   if (solver != ENKFMC_SOLVE_DUAL) return fail(ENKFMC_EINVAL, "analyze: unknown solver");
-  if (p->max_bm > 128)
-    return fail(ENKFMC_EUNSUPPORTED, "analyze: a block holds more than 128 observations (dual-form tile limit)");
   if (!p->fitted || p->fit_xb != Xb) return fail(ENKFMC_ESTATE, "analyze: needs the preceding fit on the same X_b");
   hipStream_t s = (hipStream_t)stream;
   enkfmc_status st = begin(p, s, "analyze");

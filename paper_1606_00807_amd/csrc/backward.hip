@@ -98,14 +98,16 @@ __global__ __launch_bounds__(64) void k_adj_bwd_sweep(const Block *__restrict__ 
   }
 }
 
-// P = F^T D V (ldf x N per block); one wavefront per (block, 16 member columns).
+// P = F^T D V (ldf x N per block); one wavefront per (block, 16 member columns,
+// chunk of up to 8 observation tiles).
 __global__ __launch_bounds__(64) void k_adj_ftdv(const Block *__restrict__ blocks, const double *__restrict__ F,
                                                  const double *__restrict__ dvec, const double *__restrict__ V, int N,
                                                  double *__restrict__ P) {
   constexpr int kMaxTiles = 8;
   const Block B = blocks[blockIdx.x];
-  if (B.m == 0) return;
   const int TI = B.ldf >> 4;
+  const int I0 = kMaxTiles * (int)blockIdx.z;
+  if (B.m == 0 || I0 >= TI) return;
   const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
   const int colj = 16 * blockIdx.y + c;
   const bool colok = colj < N;
@@ -122,16 +124,16 @@ __global__ __launch_bounds__(64) void k_adj_ftdv(const Block *__restrict__ block
     const double b = in ? dvec[B.row0 + k] * Vb[(int64_t)k * N + colj] : 0.0;
     const double *Fk = Fb + (int64_t)k * ldf + c;
 #pragma unroll
-    for (int I = 0; I < kMaxTiles; ++I)
-      if (I < TI) acc[I] = mfma64(Fk[16 * I], b, acc[I]);
+    for (int i = 0; i < kMaxTiles; ++i)
+      if (I0 + i < TI) acc[i] = mfma64(Fk[16 * (I0 + i)], b, acc[i]);
   }
   if (!colok) return;
   double *Pb = P + B.Q0;
 #pragma unroll
-  for (int I = 0; I < kMaxTiles; ++I) {
-    if (I < TI) {
+  for (int i = 0; i < kMaxTiles; ++i) {
+    if (I0 + i < TI) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Pb[(int64_t)(16 * I + 4 * r + q) * N + colj] = acc[I][r];
+      for (int r = 0; r < 4; ++r) Pb[(int64_t)(16 * (I0 + i) + 4 * r + q) * N + colj] = acc[i][r];
     }
   }
 }
@@ -508,7 +510,8 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   hipLaunchKernelGGL(k_adj_bwd_sweep, dim3(nb, ct), dim3(64), 0, s, d.blocks, d.ct_ptr, d.ct_row, d.ct_slot,
                      d.fit_glob, d.interior_src, d.tiles, d.tinv, dXa, N, V);
   if (p->max_bm > 0) {
-    hipLaunchKernelGGL(k_adj_ftdv, dim3(nb, ct), dim3(64), 0, s, d.blocks, d.F, d.dvec, (const double *)V, N, d.P);
+    const unsigned ot = (unsigned)((p->max_bm + 15) / 16);
+    hipLaunchKernelGGL(k_adj_ftdv, dim3(nb, ct, (ot + 7) / 8), dim3(64), 0, s, d.blocks, d.F, d.dvec, (const double *)V, N, d.P);
     hipLaunchKernelGGL(k_adj_solve_S, dim3(nb, (N + 63) / 64), dim3(64), 0, s, d.blocks, d.S, N, d.P);
   }
   hipError_t e = launch_fwd_sweep(p, d, d.P, V, d.W, s);

@@ -288,3 +288,20 @@ def instance_params(count: int = 64, config: int = 5) -> List[Dict]:
                         r_v=1 if lev > 1 else 0, obs_frac=float(g.uniform(0.02, 0.30)), R=0.05, ridge=1e-3,
                         sdx=nx // 8, sdy=ny // 8, seed=k))
     return out
+
+
+def make_instance(k: int, params: Optional[List[Dict]] = None, L_h: float = 3.0, L_v: float = 1.0, config: int = 5,
+                  dtype=np.float64) -> Problem:
+    """Instance k of the uneven batch: one variable on its own grid, FFT GRF
+    fields, observation sites and noise from streams seeded with (config, k)."""
+    d = (params or instance_params(config=config))[k]
+    geo = geometry(d["nx"], d["ny"], [d["nlev"]], periodic_x=True, sdx=d["sdx"], sdy=d["sdy"], r_h=d["r"],
+                   r_v=d["r_v"])
+    n = state_size(geo)
+    x_true = fft_grf(geo, L_h, L_v, 1, rng(config, STREAM_TRUTH, k))[:, 0]
+    Xb = fft_grf(geo, L_h, L_v, d["N"], rng(config, STREAM_ENSEMBLE, k), dtype=dtype)
+    m = int(round(d["obs_frac"] * n))
+    obs_idx = random_sites(n, m, rng(config, STREAM_OBS_SITES, k))
+    r_diag = np.full(m, d["R"])
+    Y = observe(x_true, obs_idx, r_diag, d["N"], rng(config, STREAM_OBS_NOISE, k), rng(config, STREAM_PERTURB, k))
+    return Problem(f"instance{k}", geo, d["N"], Xb, x_true, obs_idx, r_diag, Y, d["ridge"])
