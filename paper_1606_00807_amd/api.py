@@ -132,6 +132,7 @@ class Plan:
         self.ensure_workspace()
         self._check_xb(Xb)
         p, dt, ld = self._xb_args(Xb)
+        self._token = getattr(self, "_token", 0) + 1
         check(self.lib.enkfmc_fit(self._h, p, dt, ld, float(ridge), _MODES[mode], self._stream()))
 
     def analyze(self, Xb, Y, r_diag, out_dtype=None):
@@ -144,12 +145,19 @@ class Plan:
         Xa = torch.empty((self.n, self.N), dtype=out_dtype, device=Xb.device)
         p, dt, ld = self._xb_args(Xb)
         self._analysis_inputs = None
+        self._token = getattr(self, "_token", 0) + 1
         check(self.lib.enkfmc_analyze(self._h, p, dt, ld, ctypes.c_void_p(Y.data_ptr()),
                                       ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(Xa.data_ptr()),
                                       F32 if out_dtype == torch.float32 else F64, SOLVE_DUAL, self._stream()))
         # the reverse pass reads the same device copies of Y and r_diag
         self._analysis_inputs = (Y, r)
         return Xa
+
+    @property
+    def analysis_token(self) -> int:
+        """Changes with every fit and analysis; a reverse pass is valid only
+        while it equals the value read right after the matching analyze."""
+        return getattr(self, "_token", 0)
 
     def backward(self, Xb, dXa) -> Tuple:
         """dL/dX_b, dL/dlog r, dL/dridge from dL/dX_a, for the preceding

@@ -4,7 +4,9 @@ X_a = EnKF-MC analysis of X_b (eq. 1 / eq. 8 fit with ridge lam, eq. 11 local
 solves, merge of Alg. 2).  The backward pass is the library's hand-written
 adjoint (enkfmc_analyze_backward): it recomputes each regression's Gram and
 Cholesky factor instead of storing them, and returns dL/dX_b, dL/dlog r and
-dL/dlam.
+dL/dlam.  When the plan has been used since (another cycle of a chain), the
+backward pass first recomputes this call's fit and analysis on the saved
+inputs, so a chain of analyses on one plan keeps only its inputs alive.
 """
 from __future__ import annotations
 
@@ -22,6 +24,8 @@ class EnkfmcAnalysis(torch.autograd.Function):
         r = torch.exp(log_r.detach().to(torch.float64))
         Xa = plan.analyze(Xd, Y, r)
         ctx.plan = plan
+        ctx.token = plan.analysis_token
+        ctx.inputs = (plan._analysis_inputs[0], r, lam, mode)
         ctx.save_for_backward(Xd)
         ctx.meta = (Xb.dtype, log_r.dtype, ridge.dtype if isinstance(ridge, torch.Tensor) else None,
                     ridge.shape if isinstance(ridge, torch.Tensor) else None)
@@ -30,7 +34,12 @@ class EnkfmcAnalysis(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gXa):
         (Xd,) = ctx.saved_tensors
-        dXb, dlogR, dridge = ctx.plan.backward(Xd, gXa.detach())
+        plan = ctx.plan
+        if plan.analysis_token != ctx.token:
+            Yd, r, lam, mode = ctx.inputs
+            plan.fit(Xd, lam, mode=mode)
+            plan.analyze(Xd, Yd, r)
+        dXb, dlogR, dridge = plan.backward(Xd, gXa.detach())
         xdt, rdt, ldt, lshape = ctx.meta
         gl = dridge.to(ldt).reshape(lshape) if ldt is not None else None
         return dXb.to(xdt), dlogR.to(rdt), gl, None, None, None

@@ -305,3 +305,16 @@ def make_instance(k: int, params: Optional[List[Dict]] = None, L_h: float = 3.0,
     r_diag = np.full(m, d["R"])
     Y = observe(x_true, obs_idx, r_diag, d["N"], rng(config, STREAM_OBS_NOISE, k), rng(config, STREAM_PERTURB, k))
     return Problem(f"instance{k}", geo, d["N"], Xb, x_true, obs_idx, r_diag, Y, d["ridge"])
+
+
+def cycle_observations(p: Problem, cycles: int, shift: int = 1, config: int = 4) -> List[tuple]:
+    """Truth and perturbed observations of `cycles` assimilation cycles: the
+    truth of cycle t is the synthetic forecast applied t times to p.x_true
+    (cycle 0 is p's own), observed at p's fixed sites with fresh noise."""
+    out = [(np.asarray(p.x_true, np.float64), p.Y)]
+    x = np.asarray(p.x_true, np.float64)
+    for t in range(1, cycles):
+        x = linear_forecast(x, p.geometry, shift)
+        Y = observe(x, p.obs_idx, p.r_diag, p.N, rng(config, STREAM_OBS_NOISE, t), rng(config, STREAM_PERTURB, t))
+        out.append((x, Y))
+    return out
