@@ -95,10 +95,13 @@ __global__ __launch_bounds__(64) void k_build_tiles(const Block *__restrict__ bl
 }
 
 // F = T^-T H^T, backward over row tiles; one wavefront per (block, 16 observation columns).
+// T^-T is upper triangular, so the 16 columns vanish below their largest
+// observed row: those tiles are only zero-filled and the sweep starts above.
 __global__ __launch_bounds__(64) void k_bwd_sweep(const Block *__restrict__ blocks, const int64_t *__restrict__ ct_ptr,
                                                   const int32_t *__restrict__ ct_row,
                                                   const int32_t *__restrict__ ct_slot,
                                                   const int32_t *__restrict__ bobs_row,
+                                                  const int32_t *__restrict__ ot_jmax,
                                                   const double *__restrict__ tiles, const double *__restrict__ tinv,
                                                   double *__restrict__ F) {
   const Block B = blocks[blockIdx.x];
@@ -109,13 +112,20 @@ __global__ __launch_bounds__(64) void k_bwd_sweep(const Block *__restrict__ bloc
   const int jo = o < B.m ? bobs_row[B.obs0 + o] : -1;
   const int ldf = B.ldf;
   double *Fb = F + B.F0;
-  for (int C = B.nrt - 1; C >= 0; --C) {
+  const int Cs = ot_jmax[B.ot0 + oc] >> 4;
+  for (int C = B.nrt - 1; C > Cs; --C) {
+    double *Fc = Fb + (int64_t)(16 * C) * ldf + 16 * oc + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Fc[(int64_t)(4 * r + q) * ldf] = 0.0;
+  }
+  for (int C = Cs; C >= 0; --C) {
     d4 acc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = (16 * C + 4 * r + q == jo) ? 1.0 : 0.0;
     const int64_t s0 = ct_ptr[B.rt0 + C], s1 = ct_ptr[B.rt0 + C + 1];
     for (int64_t t = s0; t < s1; ++t) {
       const int R = ct_row[t];
+      if (R > Cs) continue;   // zero tile of F
       const double *Tt = tiles + (int64_t)ct_slot[t] * 256;
       const double *Fr = Fb + (int64_t)(16 * R) * ldf + 16 * oc + c;
 #pragma unroll
@@ -135,8 +145,9 @@ __global__ __launch_bounds__(64) void k_bwd_sweep(const Block *__restrict__ bloc
 // S = R + F^T D F (lower tiles, stride ldf); one wavefront per (block, tile
 // column J, chunk of up to 8 tile rows I >= J).
 __global__ __launch_bounds__(64) void k_dual_S(const Block *__restrict__ blocks, const int32_t *__restrict__ bobs_o,
-                                               const double *__restrict__ F, const double *__restrict__ dvec,
-                                               const double *__restrict__ r_diag, double *__restrict__ S) {
+                                               const int32_t *__restrict__ ot_jmax, const double *__restrict__ F,
+                                               const double *__restrict__ dvec, const double *__restrict__ r_diag,
+                                               double *__restrict__ S) {
   constexpr int kMaxTiles = 8;
   const Block B = blocks[blockIdx.x];
   const int J = blockIdx.y;
@@ -149,7 +160,8 @@ __global__ __launch_bounds__(64) void k_dual_S(const Block *__restrict__ blocks,
   d4 acc[kMaxTiles];
 #pragma unroll
   for (int I = 0; I < kMaxTiles; ++I) acc[I] = d4{0.0, 0.0, 0.0, 0.0};
-  const int ksteps = 4 * B.nrt;
+  // column tile J of F is zero below its largest observed row
+  const int ksteps = (ot_jmax[B.ot0 + J] >> 2) + 1;
   for (int ks = 0; ks < ksteps; ++ks) {
     const int k = 4 * ks + q;
     const double dk = k < B.n ? dvec[B.row0 + k] : 0.0;
@@ -237,9 +249,10 @@ __global__ __launch_bounds__(64) void k_dual_Q(const Block *__restrict__ blocks,
 // G = D (F Q) of row tile R (or D (V - F Q) with V given), written into the
 // output rows that the forward sweep then solves in place.  One wavefront per
 // (block, row tile); it loops over the 16-member column tiles.
-__global__ __launch_bounds__(64) void k_dual_G(const Block *__restrict__ blocks, const double *__restrict__ F,
-                                               const double *__restrict__ Q, const double *__restrict__ dvec,
-                                               const double *__restrict__ V, int N, double *__restrict__ G) {
+__global__ __launch_bounds__(64) void k_dual_G(const Block *__restrict__ blocks, const int32_t *__restrict__ ot_jmax,
+                                               const double *__restrict__ F, const double *__restrict__ Q,
+                                               const double *__restrict__ dvec, const double *__restrict__ V, int N,
+                                               double *__restrict__ G) {
   const Block B = blocks[blockIdx.x];
   const int R = blockIdx.y;
   if (R >= B.nrt) return;
@@ -258,9 +271,14 @@ __global__ __launch_bounds__(64) void k_dual_G(const Block *__restrict__ blocks,
     const bool colok = colj < N;
     const int coll = colok ? colj : 0;
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-    for (int ks = 0; ks < (ldf >> 2); ++ks) {
-      const double bq = Qb[(int64_t)(4 * ks + q) * N + coll];
-      acc = mfma64(Fr[4 * ks], colok ? bq : 0.0, acc);
+    for (int t = 0; t < (ldf >> 4); ++t) {
+      if (ot_jmax[B.ot0 + t] < 16 * R) continue;   // F_R is zero in these 16 columns
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int ks = 4 * t + kk;
+        const double bq = Qb[(int64_t)(4 * ks + q) * N + coll];
+        acc = mfma64(Fr[4 * ks], colok ? bq : 0.0, acc);
+      }
     }
     if (!colok) continue;
 #pragma unroll
@@ -350,8 +368,8 @@ hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const
                             hipStream_t s) {
   const unsigned nb = (unsigned)p->blocks.size();
   phase_begin(p, ENKFMC_PH_DUAL_G, s);
-  hipLaunchKernelGGL(k_dual_G, dim3(nb, (unsigned)max_block_tiles(p)), dim3(64), 0, s, d.blocks, d.F, Q, d.dvec, V,
-                     p->N, out);
+  hipLaunchKernelGGL(k_dual_G, dim3(nb, (unsigned)max_block_tiles(p)), dim3(64), 0, s, d.blocks, d.ot_jmax, d.F, Q,
+                     d.dvec, V, p->N, out);
   phase_end(p, ENKFMC_PH_DUAL_G, s);
   phase_begin(p, ENKFMC_PH_SWEEP, s);
   hipLaunchKernelGGL(k_fwd_sweep, dim3(nb, (p->N + 15) / 16), dim3(64), 0, s, d.blocks, d.rt_ptr, d.rt_col, d.rt_slot,
@@ -369,10 +387,11 @@ static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   if (p->max_bm > 0) {
     phase_begin(p, ENKFMC_PH_DUAL_F, s);
     hipLaunchKernelGGL(k_bwd_sweep, dim3(nb, oc), dim3(64), 0, s, d.blocks, d.ct_ptr, d.ct_row, d.ct_slot, d.bobs_row,
-                       d.tiles, d.tinv, d.F);
+                       d.ot_jmax, d.tiles, d.tinv, d.F);
     phase_end(p, ENKFMC_PH_DUAL_F, s);
     phase_begin(p, ENKFMC_PH_DUAL_S, s);
-    hipLaunchKernelGGL(k_dual_S, dim3(nb, oc, (oc + 7) / 8), dim3(64), 0, s, d.blocks, d.bobs_o, d.F, d.dvec, r_diag, d.S);
+    hipLaunchKernelGGL(k_dual_S, dim3(nb, oc, (oc + 7) / 8), dim3(64), 0, s, d.blocks, d.bobs_o, d.ot_jmax, d.F,
+                       d.dvec, r_diag, d.S);
     phase_end(p, ENKFMC_PH_DUAL_S, s);
     phase_begin(p, ENKFMC_PH_DUAL_CHOL, s);
     hipLaunchKernelGGL(k_dual_chol, dim3(nb), dim3(256), 0, s, d.blocks, d.S, d.status);

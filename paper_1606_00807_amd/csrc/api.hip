@@ -138,6 +138,7 @@ enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes,
   HIPCHK(put(p, L.o2b_ptr, p->o2b_ptr, s), "set_workspace");
   HIPCHK(put(p, L.o2b, p->o2b, s), "set_workspace");
   HIPCHK(put(p, L.bobs_fit, p->bobs_fit, s), "set_workspace");
+  HIPCHK(put(p, L.ot_jmax, p->ot_jmax, s), "set_workspace");
   HIPCHK(put(p, L.rt_ptr, p->rt_ptr, s), "set_workspace");
   HIPCHK(put(p, L.rt_col, p->rt_col, s), "set_workspace");
   HIPCHK(put(p, L.rt_slot, p->rt_slot, s), "set_workspace");

@@ -100,9 +100,9 @@ __global__ __launch_bounds__(64) void k_adj_bwd_sweep(const Block *__restrict__ 
 
 // P = F^T D V (ldf x N per block); one wavefront per (block, 16 member columns,
 // chunk of up to 8 observation tiles).
-__global__ __launch_bounds__(64) void k_adj_ftdv(const Block *__restrict__ blocks, const double *__restrict__ F,
-                                                 const double *__restrict__ dvec, const double *__restrict__ V, int N,
-                                                 double *__restrict__ P) {
+__global__ __launch_bounds__(64) void k_adj_ftdv(const Block *__restrict__ blocks, const int32_t *__restrict__ ot_jmax,
+                                                 const double *__restrict__ F, const double *__restrict__ dvec,
+                                                 const double *__restrict__ V, int N, double *__restrict__ P) {
   constexpr int kMaxTiles = 8;
   const Block B = blocks[blockIdx.x];
   const int TI = B.ldf >> 4;
@@ -117,7 +117,10 @@ __global__ __launch_bounds__(64) void k_adj_ftdv(const Block *__restrict__ block
   d4 acc[kMaxTiles];
 #pragma unroll
   for (int I = 0; I < kMaxTiles; ++I) acc[I] = d4{0.0, 0.0, 0.0, 0.0};
-  const int ksteps = 4 * B.nrt;
+  // the chunk's columns of F vanish below their largest observed row
+  int jm = 0;
+  for (int i = 0; i < kMaxTiles && I0 + i < TI; ++i) jm = max(jm, ot_jmax[B.ot0 + I0 + i]);
+  const int ksteps = (jm >> 2) + 1;
   for (int ks = 0; ks < ksteps; ++ks) {
     const int k = 4 * ks + q;
     const bool in = k < B.n && colok;
@@ -511,7 +514,8 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
                      d.fit_glob, d.interior_src, d.tiles, d.tinv, dXa, N, V);
   if (p->max_bm > 0) {
     const unsigned ot = (unsigned)((p->max_bm + 15) / 16);
-    hipLaunchKernelGGL(k_adj_ftdv, dim3(nb, ct, (ot + 7) / 8), dim3(64), 0, s, d.blocks, d.F, d.dvec, (const double *)V, N, d.P);
+    hipLaunchKernelGGL(k_adj_ftdv, dim3(nb, ct, (ot + 7) / 8), dim3(64), 0, s, d.blocks, d.ot_jmax, d.F, d.dvec,
+                       (const double *)V, N, d.P);
     hipLaunchKernelGGL(k_adj_solve_S, dim3(nb, (N + 63) / 64), dim3(64), 0, s, d.blocks, d.S, N, d.P);
   }
   hipError_t e = launch_fwd_sweep(p, d, d.P, V, d.W, s);

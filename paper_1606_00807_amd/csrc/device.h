@@ -18,7 +18,7 @@ struct Dev {
   const int64_t *g2f_ptr;
   const int32_t *g2f;
   const int64_t *o2b_ptr;
-  const int32_t *o2b, *bobs_fit;
+  const int32_t *o2b, *bobs_fit, *ot_jmax;
   const int64_t *rt_ptr, *ct_ptr;
   const int32_t *rt_col, *rt_slot, *ct_row, *ct_slot;
   double *tiles, *tinv;
@@ -47,6 +47,7 @@ inline Dev make_dev(enkfmc_plan *p) {
   d.o2b_ptr = (const int64_t *)(w + L.o2b_ptr);
   d.o2b = (const int32_t *)(w + L.o2b);
   d.bobs_fit = (const int32_t *)(w + L.bobs_fit);
+  d.ot_jmax = (const int32_t *)(w + L.ot_jmax);
   d.rt_ptr = (const int64_t *)(w + L.rt_ptr);
   d.rt_col = (const int32_t *)(w + L.rt_col);
   d.rt_slot = (const int32_t *)(w + L.rt_slot);

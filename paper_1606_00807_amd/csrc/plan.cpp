@@ -166,7 +166,7 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
       br[b].push_back((l * sb.BY + (lat - sb.ys)) * sb.BX + ix);
     }
   }
-  p->bobs_o.clear(); p->bobs_row.clear(); p->bobs_fit.clear();
+  p->bobs_o.clear(); p->bobs_row.clear(); p->bobs_fit.clear(); p->ot_jmax.clear();
   p->o2b_ptr.assign(m + 1, 0);
   int64_t sumF = 0, sumS = 0, sumQ = 0;
   for (size_t b = 0; b < p->blocks.size(); ++b) {
@@ -178,6 +178,14 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
     B.F0 = sumF; B.S0 = sumS; B.Q0 = sumQ;
     sumF += (int64_t)16 * B.nrt * B.ldf; sumS += (int64_t)B.ldf * B.ldf; sumQ += (int64_t)B.ldf * N;
     p->max_bm = std::max(p->max_bm, B.m);
+    // column o of F = T^-T H^T vanishes below its observed row, so each tile of
+    // 16 observations is zero below the largest of its rows
+    B.ot0 = (int64_t)p->ot_jmax.size();
+    for (int32_t t = 0; t < B.ldf / 16; ++t) {
+      int32_t jm = -1;
+      for (int32_t a = 16 * t; a < std::min(B.m, 16 * t + 16); ++a) jm = std::max(jm, br[b][a]);
+      p->ot_jmax.push_back(jm);
+    }
     for (size_t t = 0; t < bo[b].size(); ++t) {
       p->bobs_o.push_back(bo[b][t]);
       p->bobs_row.push_back(br[b][t]);
@@ -288,6 +296,7 @@ void compute_layout(enkfmc_plan *p) {
   L.o2b_ptr = take((m + 1) * 8);
   L.o2b = take(ml * 4);
   L.bobs_fit = take(ml * 4);
+  L.ot_jmax = take(p->ot_jmax.size() * 4 + 4);
   L.rt_ptr = take((size_t)(p->n_rt + 1) * 8);
   L.rt_col = take(p->rt_col.size() * 4);
   L.rt_slot = take(p->rt_slot.size() * 4);

@@ -27,6 +27,7 @@ struct Block {
   int32_t nrt;           // 16-row tiles of the block (the last one may be partial)
   int32_t ldf;           // observation count rounded up to 16
   int64_t rt0;           // first row tile (global row-tile numbering)
+  int64_t ot0;           // first observation tile (global numbering; ldf / 16 tiles)
 };
 
 struct SubBox {
@@ -38,7 +39,7 @@ struct SubBox {
 // Offsets (bytes) of every device array inside the workspace.
 struct Layout {
   size_t blocks, fit_glob, fit_blk, fit_rows, row_ptr, col, csc_ptr, csc_row, csc_nz, interior_src, bobs_o, bobs_row;
-  size_t g2f_ptr, g2f, o2b_ptr, o2b, bobs_fit;
+  size_t g2f_ptr, g2f, o2b_ptr, o2b, bobs_fit, ot_jmax;
   size_t rt_ptr, rt_col, rt_slot, ct_ptr, ct_row, ct_slot;
   size_t tval, dvec, mean, U, Z, F, S, Q, P, W, aux1, aux2, aux3, dbar, red, tiles, tinv, status;
   size_t total;
@@ -66,6 +67,7 @@ struct enkfmc_plan {
   std::vector<int32_t> interior_src;            // n: fit row that maps back onto each component
   std::vector<int32_t> bobs_o, bobs_row;        // per block observation list
   std::vector<int32_t> bobs_fit;                // fit row of each block observation
+  std::vector<int32_t> ot_jmax;                 // per observation tile: largest local row observed in it
   std::vector<int64_t> g2f_ptr;                 // n + 1: fit rows holding each component, sub-domain order
   std::vector<int32_t> g2f;
   std::vector<int64_t> o2b_ptr;                 // m + 1: block-observation entries of each observation
