@@ -234,15 +234,9 @@ __global__ __launch_bounds__(64) void k_dual_Q(const Block *__restrict__ blocks,
   for (int a = 0; a < m; ++a) {
     const int o = bobs_o[B.obs0 + a];
     const int64_t g = fit_glob[B.row0 + bobs_row[B.obs0 + a]];
-    double acc = Y[(int64_t)o * N + c] - (double)Xb[g * ld + c];
-    for (int b = 0; b < a; ++b) acc -= L[(int64_t)a * lds + b] * q[(int64_t)b * N + c];
-    q[(int64_t)a * N + c] = acc / L[(int64_t)a * lds + a];
+    q[(int64_t)a * N + c] = Y[(int64_t)o * N + c] - (double)Xb[g * ld + c];
   }
-  for (int a = m - 1; a >= 0; --a) {
-    double acc = q[(int64_t)a * N + c];
-    for (int b = a + 1; b < m; ++b) acc -= L[(int64_t)b * lds + a] * q[(int64_t)b * N + c];
-    q[(int64_t)a * N + c] = acc / L[(int64_t)a * lds + a];
-  }
+  chol_solve_col(L, lds, m, q + c, N);
   for (int a = m; a < lds; ++a) q[(int64_t)a * N + c] = 0.0;
 }
 

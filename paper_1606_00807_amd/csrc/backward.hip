@@ -150,16 +150,7 @@ __global__ __launch_bounds__(64) void k_adj_solve_S(const Block *__restrict__ bl
   const int m = B.m, lds = B.ldf;
   const double *L = S + B.S0;
   double *x = P + B.Q0;
-  for (int a = 0; a < m; ++a) {
-    double acc = x[(int64_t)a * N + c];
-    for (int b = 0; b < a; ++b) acc -= L[(int64_t)a * lds + b] * x[(int64_t)b * N + c];
-    x[(int64_t)a * N + c] = acc / L[(int64_t)a * lds + a];
-  }
-  for (int a = m - 1; a >= 0; --a) {
-    double acc = x[(int64_t)a * N + c];
-    for (int b = a + 1; b < m; ++b) acc -= L[(int64_t)b * lds + a] * x[(int64_t)b * N + c];
-    x[(int64_t)a * N + c] = acc / L[(int64_t)a * lds + a];
-  }
+  chol_solve_col(L, lds, m, x + c, N);
   for (int a = m; a < lds; ++a) x[(int64_t)a * N + c] = 0.0;
 }
 

@@ -98,6 +98,57 @@ __device__ inline double block_sum256(double s, double *red) {
 
 template <typename T> __device__ inline double ld_as_double(const T *p) { return (double)(*p); }
 
+// In-place solve L L^T x = x for one column x (stride sx) with the lower
+// Cholesky factor L (m x m, row stride ld), eight rows at a time: each loaded
+// x_b serves eight independent accumulations.
+__device__ inline void chol_solve_col(const double *__restrict__ L, int ld, int m, double *__restrict__ x,
+                                      int64_t sx) {
+  constexpr int kB = 8;
+  for (int a0 = 0; a0 < m; a0 += kB) {          // forward: L y = x
+    double acc[kB];
+#pragma unroll
+    for (int i = 0; i < kB; ++i) acc[i] = a0 + i < m ? x[(int64_t)(a0 + i) * sx] : 0.0;
+    for (int b = 0; b < a0; ++b) {
+      const double xb = x[(int64_t)b * sx];
+#pragma unroll
+      for (int i = 0; i < kB; ++i)
+        if (a0 + i < m) acc[i] = fma(-L[(int64_t)(a0 + i) * ld + b], xb, acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int a = a0 + i;
+      if (a < m) {
+#pragma unroll
+        for (int j = 0; j < i; ++j) acc[i] = fma(-L[(int64_t)a * ld + a0 + j], acc[j], acc[i]);
+        acc[i] /= L[(int64_t)a * ld + a];
+        x[(int64_t)a * sx] = acc[i];
+      }
+    }
+  }
+  const int top = (m - 1) / kB * kB;
+  for (int a0 = top; a0 >= 0; a0 -= kB) {       // backward: L^T x = y
+    double acc[kB];
+#pragma unroll
+    for (int i = 0; i < kB; ++i) acc[i] = a0 + i < m ? x[(int64_t)(a0 + i) * sx] : 0.0;
+    for (int b = a0 + kB; b < m; ++b) {
+      const double xb = x[(int64_t)b * sx];
+#pragma unroll
+      for (int i = 0; i < kB; ++i) acc[i] = fma(-L[(int64_t)b * ld + a0 + i], xb, acc[i]);
+    }
+#pragma unroll
+    for (int i = kB - 1; i >= 0; --i) {
+      const int a = a0 + i;
+      if (a < m) {
+#pragma unroll
+        for (int j = i + 1; j < kB; ++j)
+          if (a0 + j < m) acc[i] = fma(-L[(int64_t)(a0 + j) * ld + a], acc[j], acc[i]);
+        acc[i] /= L[(int64_t)a * ld + a];
+        x[(int64_t)a * sx] = acc[i];
+      }
+    }
+  }
+}
+
 // Phase timing: records a HIP event pair around a kernel when the plan asks for it.
 inline void phase_begin(enkfmc_plan *p, int ph, hipStream_t s) {
   if (!p->timing) return;
