@@ -278,15 +278,21 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       }
 
   // ---- 3. blocked Cholesky of the bordered matrix -------------------------
-  // L.col holds column k of the current panel: element of row 16I + 4rr + q
-  // at 16I + 4q + rr; the bordering row sits at 16T.
+  // Per panel J: the 16 columns of the diagonal tile are eliminated one at a
+  // time, carrying an identity tile E along as extra rows, so that E ends as
+  // L_JJ^-T; the tiles below then follow as L_IJ = A_IJ L_JJ^-T by MFMA.
+  // L.col holds column k of the diagonal tile at 16J + 4q + rr (row 4rr + q),
+  // that of E at 16J + 16 + 4q + rr, and the bordering row's entry at 16T.
+  // Columns stay unscaled during the elimination: column k is broadcast as is
+  // and the update uses a[i][k] a[j][k] / piv_k.  At the end each column c is
+  // scaled once by its 1/L_cc, which also turns its final pivot into L_cc.
 #pragma unroll
   for (int J = 0; J < T; ++J) {
+    const bool below = J + 1 < T;
+    d4 eid;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) eid[rr] = (4 * rr + q == c) ? 1.0 : 0.0;
     // pivot of the panel's first column (after the trailing updates)
-    // Columns stay unscaled while the panel is eliminated: column k is
-    // broadcast as is and the update uses a[i][k] a[j][k] / piv_k.  At the end
-    // of the panel each column c is scaled once by its 1/L_cc, which also turns
-    // its final pivot on the diagonal into L_cc.
     double piv = readlane_d(acc[tix<T>(J, J)][0], 0);
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
@@ -297,8 +303,8 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       const double inv = rsqrt_nr(piv);
       if (lane == 0) L.dinv[16 * J + kk] = inv;
       if (c == kk) {
-#pragma unroll
-        for (int I = J; I < T; ++I) *(d4 *)&L.col[16 * I + 4 * q] = acc[tix<T>(I, J)];
+        *(d4 *)&L.col[16 * J + 4 * q] = acc[tix<T>(J, J)];
+        if (below) *(d4 *)&L.col[16 * J + 16 + 4 * q] = eid;
         if (q == 0) {
           augv[J] *= inv;
           L.col[16 * T] = augv[J];
@@ -317,21 +323,44 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       const double colv = L.col[16 * J + 4 * (c & 3) + (c >> 2)];
       const double cv1 = c > kk ? colv * inv : 0.0;   // L[16J + c][k]
       const double cv2 = cv1 * inv;
-#pragma unroll
-      for (int I = J; I < T; ++I) {
-        const d4 rowv = *(const d4 *)&L.col[16 * I + 4 * q];
-        d4 v = acc[tix<T>(I, J)];
+      {
+        const d4 rowv = *(const d4 *)&L.col[16 * J + 4 * q];
+        d4 v = acc[tix<T>(J, J)];
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) v[rr] = fma(-rowv[rr], cv2, v[rr]);
-        acc[tix<T>(I, J)] = v;
+        acc[tix<T>(J, J)] = v;
+      }
+      if (below) {
+        const d4 rowe = *(const d4 *)&L.col[16 * J + 16 + 4 * q];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) eid[rr] = fma(-rowe[rr], cv2, eid[rr]);
       }
       augv[J] = fma(-L.col[16 * T], cv1, augv[J]);
       wave_lds_sync();
     }
     {
       const double myinv = L.dinv[16 * J + c];
+      acc[tix<T>(J, J)] *= myinv;
+      eid *= myinv;   // L_JJ^-T; the accumulator layout is the B operand layout
+    }
+    if (below) {
+      // L_IJ = A_IJ L_JJ^-T, the A operand transposed through LDS
 #pragma unroll
-      for (int I = J; I < T; ++I) acc[tix<T>(I, J)] *= myinv;
+      for (int I = J + 1; I < T; ++I) {
+        double *tb = L.tile + (I - J - 1) * 16 * kTileLd;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) tb[(4 * rr + q) * kTileLd + c] = acc[tix<T>(I, J)][rr];
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int I = J + 1; I < T; ++I) {
+        const double *tb = L.tile + (I - J - 1) * 16 * kTileLd;
+        d4 a = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) a = mfma64(tb[c * kTileLd + 4 * kc + q], eid[kc], a);
+        acc[tix<T>(I, J)] = a;
+      }
+      wave_lds_sync();
     }
     if (J + 1 < T) {
       // transpose the panel tiles below the diagonal into LDS (row-major, padded);
