@@ -49,8 +49,8 @@ def fit_flops(counts, N):
 # counters, each scaled by what the same counter reads for a plain copy of
 # known size.  Valid only for the kernel source it was taken on: a changed
 # source reports null.
-TRAFFIC = {"fit_batched_sha256": "3fc1ae83e4a6188248003c73ac8a0824e9ff785e5233d415c765335b290a1bb8",
-           "fetch_bytes": 1.1786e10, "write_bytes": 2.0307e9, "bytes_per_launch": 1.3817e10,
+TRAFFIC = {"fit_batched_sha256": "4655ca086eca5df3d5726a9787c7b57fc65647e55aa2f5f6034d557e9c844aca",
+           "fetch_bytes": 1.2446e10, "write_bytes": 2.0313e9, "bytes_per_launch": 1.4477e10,
            "fetch_scale": 1.9999, "write_scale": 1.0}
 
 
