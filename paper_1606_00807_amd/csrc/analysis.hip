@@ -39,7 +39,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(const Block *__restrict__ bl
                                                     const int64_t *__restrict__ rt_ptr,
                                                     const int32_t *__restrict__ rt_col,
                                                     const int32_t *__restrict__ rt_slot, double *__restrict__ tiles,
-                                                    double *__restrict__ tinv) {
+                                                    double *__restrict__ tinv, double *__restrict__ tdiag) {
   __shared__ double diag[256];
   const Block B = blocks[blockIdx.x];
   const int R = blockIdx.y;
@@ -77,6 +77,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(const Block *__restrict__ bl
     for (int j = 0; j < 16; j += 2) *(d2 *)(dst + j) = d2{v[j], v[j + 1]};
   }
   __syncthreads();
+  for (int e = lane; e < 256; e += 64) tdiag[rt * 256 + e] = diag[e];   // strictly lower T_RR
   if (lane < 16) {
     // column `lane` of (I + L)^-1 by forward substitution
     const int j = lane;
@@ -353,7 +354,7 @@ int max_block_tiles(const enkfmc_plan *p) {
 hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s) {
   phase_begin(p, ENKFMC_PH_TILES, s);
   hipLaunchKernelGGL(k_build_tiles, dim3((unsigned)p->blocks.size(), (unsigned)max_block_tiles(p)), dim3(64), 0, s,
-                     d.blocks, d.row_ptr, d.col, d.tval, d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tinv);
+                     d.blocks, d.row_ptr, d.col, d.tval, d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tinv, d.tdiag);
   phase_end(p, ENKFMC_PH_TILES, s);
   return hipGetLastError();
 }

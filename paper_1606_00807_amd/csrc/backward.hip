@@ -154,65 +154,116 @@ __global__ __launch_bounds__(64) void k_adj_solve_S(const Block *__restrict__ bl
   for (int a = m; a < lds; ++a) x[(int64_t)a * N + c] = 0.0;
 }
 
-// Dbar_i and betabar_i of every fit row; one wavefront per row, N <= 128.
-__global__ __launch_bounds__(256) void k_adj_factor_bar(const Block *__restrict__ blocks,
-                                                        const int32_t *__restrict__ fit_blk,
-                                                        const int64_t *__restrict__ row_ptr,
-                                                        const int32_t *__restrict__ col,
-                                                        const double *__restrict__ tval,
-                                                        const double *__restrict__ dvec, const double *__restrict__ Z,
-                                                        const double *__restrict__ W, int64_t n_fit, int N,
-                                                        double *__restrict__ dbar, double *__restrict__ bbar) {
-  __shared__ double sa[4][128], sb[4][128];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + wave;
-  if (r >= n_fit) return;
-  const Block B = blocks[fit_blk[r]];
-  const int64_t lo = row_ptr[r];
-  const int p = (int)(row_ptr[r + 1] - lo);
-  const double d = dvec[r];
-  double tz[2], tw[2];
+// Dbar and betabar by 16-row tiles of T.  One wavefront per (block, row tile
+// R): TZ_R = Z_R + sum_C T_RC Z_C and TW_R likewise (C over the pattern's
+// tiles of R, the strictly lower T_RR included) by MFMA, kept in LDS scaled by
+// 1/d; Dbar_i = (TW)_i . (TZ)_i / d_i^2; then per tile (R, C) of the pattern
+// the 16 x 16 products (TZ_R/d) W_C^T + (TW_R/d) Z_C^T, of which the entries in
+// the pattern of T are betabar, written in CSR order.  LDS: 2 x 16 x (N + 1) + 16 x 17 doubles.
+__global__ __launch_bounds__(64) void k_adj_factor_tiles(const Block *__restrict__ blocks,
+                                                         const int64_t *__restrict__ row_ptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const int64_t *__restrict__ rt_ptr,
+                                                         const int32_t *__restrict__ rt_col,
+                                                         const int32_t *__restrict__ rt_slot,
+                                                         const double *__restrict__ tiles,
+                                                         const double *__restrict__ tdiag,
+                                                         const double *__restrict__ dvec, const double *__restrict__ Z,
+                                                         const double *__restrict__ W, int N,
+                                                         double *__restrict__ dbar, double *__restrict__ bbar) {
+  extern __shared__ double sm[];
+  const Block B = blocks[blockIdx.x];
+  const int R = blockIdx.y;
+  if (R >= B.nrt) return;
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int ldn = N + 1;
+  double *sTZ = sm, *sTW = sm + 16 * ldn, *sout = sm + 32 * ldn;
+  const int64_t rt = B.rt0 + R;
+  const int64_t t0 = rt_ptr[rt];
+  const int nt = (int)(rt_ptr[rt + 1] - t0);
+  const double *Zb = Z + B.row0 * N, *Wb = W + B.row0 * N;
+  double dinv[4], dpart[4];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int cc = lane + 64 * h;
-    tz[h] = cc < N ? Z[r * N + cc] : 0.0;
-    tw[h] = cc < N ? W[r * N + cc] : 0.0;
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * R + 4 * r + q;
+    dinv[r] = row < B.n ? 1.0 / dvec[B.row0 + row] : 0.0;
+    dpart[r] = 0.0;
   }
-  for (int k = 0; k < p; ++k) {
-    const int64_t f = B.row0 + col[lo + k];
-    const double t = tval[lo + k];
+  for (int cc = 0; 16 * cc < N; ++cc) {
+    const int colj = 16 * cc + c;
+    const bool colok = colj < N;
+    d4 az, aw;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int cc = lane + 64 * h;
-      if (cc < N) {
-        tz[h] = fma(t, Z[f * N + cc], tz[h]);
-        tw[h] = fma(t, W[f * N + cc], tw[h]);
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * R + 4 * r + q;
+      const bool in = row < B.n && colok;
+      az[r] = in ? Zb[(int64_t)row * N + colj] : 0.0;
+      aw[r] = in ? Wb[(int64_t)row * N + colj] : 0.0;
+    }
+    for (int t = 0; t <= nt; ++t) {            // t == nt: the diagonal tile
+      const int C = t < nt ? rt_col[t0 + t] : R;
+      const double *Tt = t < nt ? tiles + (int64_t)rt_slot[t0 + t] * 256 : tdiag + rt * 256;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        const double a = Tt[c * 16 + 4 * kc + q];
+        const int zr = 16 * C + 4 * kc + q;
+        const bool in = zr < B.n && colok;
+        az = mfma64(a, in ? Zb[(int64_t)zr * N + colj] : 0.0, az);
+        aw = mfma64(a, in ? Wb[(int64_t)zr * N + colj] : 0.0, aw);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      dpart[r] = fma(az[r], aw[r], dpart[r]);
+      if (colok) {
+        sTZ[(4 * r + q) * ldn + colj] = az[r] * dinv[r];
+        sTW[(4 * r + q) * ldn + colj] = aw[r] * dinv[r];
       }
     }
   }
-  const double s = wave_sum(tz[0] * tw[0] + tz[1] * tw[1]);
-  if (lane == 0) dbar[r] = s / (d * d);
-  const double inv = 1.0 / d;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    sa[wave][lane + 64 * h] = tz[h] * inv;
-    sb[wave][lane + 64 * h] = tw[h] * inv;
+  for (int r = 0; r < 4; ++r) {
+    double v = dpart[r];
+    v += __shfl_xor(v, 8, 16);
+    v += __shfl_xor(v, 4, 16);
+    v += __shfl_xor(v, 2, 16);
+    v += __shfl_xor(v, 1, 16);
+    const int row = 16 * R + 4 * r + q;
+    if (c == 0 && row < B.n) dbar[B.row0 + row] = v * dinv[r] * dinv[r];
   }
   wave_lds_sync();
-  // 16 lanes per predecessor, four predecessors at a time
-  const int g = lane >> 4, l16 = lane & 15;
-  for (int k0 = 0; k0 < p; k0 += 4) {
-    const int k = k0 + g;
-    double acc = 0.0;
-    if (k < p) {
-      const int64_t f = B.row0 + col[lo + k];
-      for (int cc = l16; cc < N; cc += 16) acc += sa[wave][cc] * W[f * N + cc] + sb[wave][cc] * Z[f * N + cc];
+  for (int t = 0; t <= nt; ++t) {
+    const int C = t < nt ? rt_col[t0 + t] : R;
+    const int jr = 16 * C + c;                 // row of W_C, Z_C for the B operand
+    const bool jin = jr < B.n;
+    d4 o = d4{0.0, 0.0, 0.0, 0.0};
+    for (int ks = 0; 4 * ks < N; ++ks) {
+      const int k = 4 * ks + q;
+      const bool kin = k < N;
+      const double a1 = kin ? sTZ[c * ldn + k] : 0.0;
+      const double a2 = kin ? sTW[c * ldn + k] : 0.0;
+      const double bw = (jin && kin) ? Wb[(int64_t)jr * N + k] : 0.0;
+      const double bz = (jin && kin) ? Zb[(int64_t)jr * N + k] : 0.0;
+      o = mfma64(a1, bw, o);
+      o = mfma64(a2, bz, o);
     }
-    acc += __shfl_xor(acc, 8, 16);
-    acc += __shfl_xor(acc, 4, 16);
-    acc += __shfl_xor(acc, 2, 16);
-    acc += __shfl_xor(acc, 1, 16);
-    if (k < p && l16 == 0) bbar[lo + k] = acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sout[(4 * r + q) * 17 + c] = o[r];
+    wave_lds_sync();
+    if (lane < 16) {
+      const int row = 16 * R + lane;
+      if (row < B.n) {
+        const int64_t ka = row_ptr[B.row0 + row], kb = row_ptr[B.row0 + row + 1];
+        int64_t lo = ka, hi = kb;              // first entry with col >= 16C
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (col[mid] < 16 * C) lo = mid + 1;
+          else hi = mid;
+        }
+        for (int64_t k = lo; k < kb && col[k] < 16 * C + 16; ++k) bbar[k] = sout[lane * 17 + col[k] - 16 * C];
+      }
+    }
+    wave_lds_sync();
   }
 }
 
@@ -481,14 +532,17 @@ __global__ __launch_bounds__(256) void k_adj_obs(const int64_t *__restrict__ o2b
   }
 }
 
-// dL/dlam = sum of the rows' shares, in a fixed order.
-__global__ __launch_bounds__(256) void k_adj_lambda(const double *__restrict__ lam_row, int64_t n_fit,
-                                                    double *__restrict__ dridge) {
+// dL/dlam = sum of the rows' shares, in a fixed order: workgroup g sums the
+// contiguous chunk g (fixed chunking), then one workgroup sums the partials.
+__global__ __launch_bounds__(256) void k_adj_lambda(const double *__restrict__ v, int64_t n, int64_t chunk,
+                                                    double *__restrict__ out) {
   __shared__ double red[8];
+  const int64_t b0 = (int64_t)blockIdx.x * chunk;
+  const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n_fit; i += 256) s += lam_row[i];
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) s += v[i];
   s = block_sum256(s, red);
-  if (threadIdx.x == 0) dridge[0] = s;
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 template <typename TX>
@@ -512,10 +566,15 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   hipError_t e = launch_fwd_sweep(p, d, d.P, V, d.W, s);
   if (e != hipSuccess) return e;
   phase_end(p, ENKFMC_PH_ADJ_SOLVE, s);
-  const unsigned gr = (unsigned)((p->n_fit + 3) / 4);
   phase_begin(p, ENKFMC_PH_ADJ_FACTOR, s);
-  hipLaunchKernelGGL(k_adj_factor_bar, dim3(gr), dim3(256), 0, s, d.blocks, d.fit_blk, d.row_ptr, d.col, d.tval,
-                     d.dvec, d.Z, d.W, p->n_fit, N, d.dbar, d.aux3);
+  {
+    const size_t lds = (size_t)(32 * (N + 1) + 16 * 17) * 8;
+    e = hipFuncSetAttribute((const void *)k_adj_factor_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_factor_tiles, dim3(nb, (unsigned)max_block_tiles(p)), dim3(64), lds, s, d.blocks,
+                       d.row_ptr, d.col, d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tdiag, d.dvec, d.Z, d.W, N, d.dbar,
+                       d.aux3);
+  }
   phase_end(p, ENKFMC_PH_ADJ_FACTOR, s);
   phase_begin(p, ENKFMC_PH_ADJ_REGRESS, s);
   if (p->fit_mode == ENKFMC_FIT_PLAIN || launch_adj_regress_batched(p, d, lam, s) == hipErrorNotSupported) {
@@ -534,7 +593,13 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   if (p->m > 0)
     hipLaunchKernelGGL(k_adj_obs<TX>, dim3((unsigned)((p->m + 3) / 4)), dim3(256), 0, s, d.o2b_ptr, d.o2b,
                        d.bobs_fit, d.fit_glob, d.Z, d.W, Y, Xb, ld, r_diag, p->m, N, dXb, dlogR);
-  hipLaunchKernelGGL(k_adj_lambda, dim3(1), dim3(256), 0, s, d.red, p->n_fit, dridge);
+  {
+    constexpr int kParts = 256;   // partial sums land in dbar, free by now
+    const int64_t chunk = (p->n_fit + kParts - 1) / kParts;
+    hipLaunchKernelGGL(k_adj_lambda, dim3(kParts), dim3(256), 0, s, (const double *)d.red, p->n_fit, chunk, d.dbar);
+    hipLaunchKernelGGL(k_adj_lambda, dim3(1), dim3(256), 0, s, (const double *)d.dbar, (int64_t)kParts,
+                       (int64_t)kParts, dridge);
+  }
   phase_end(p, ENKFMC_PH_ADJ_GATHER, s);
   phase_end(p, ENKFMC_PH_BACKWARD, s);
   return hipGetLastError();

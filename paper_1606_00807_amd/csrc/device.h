@@ -21,7 +21,7 @@ struct Dev {
   const int32_t *o2b, *bobs_fit, *ot_jmax;
   const int64_t *rt_ptr, *ct_ptr;
   const int32_t *rt_col, *rt_slot, *ct_row, *ct_slot;
-  double *tiles, *tinv;
+  double *tiles, *tinv, *tdiag;
   double *tval, *dvec, *mean, *U, *Z, *F, *S, *Q, *P, *W, *aux1, *aux2, *aux3, *dbar, *red;
   int32_t *status;
 };
@@ -56,6 +56,7 @@ inline Dev make_dev(enkfmc_plan *p) {
   d.ct_slot = (const int32_t *)(w + L.ct_slot);
   d.tiles = (double *)(w + L.tiles);
   d.tinv = (double *)(w + L.tinv);
+  d.tdiag = (double *)(w + L.tdiag);
   d.tval = (double *)(w + L.tval);
   d.dvec = (double *)(w + L.dvec);
   d.mean = (double *)(w + L.mean);
@@ -165,6 +166,7 @@ hipError_t launch_anomaly(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t 
 hipError_t launch_fit_plain(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
 hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
 hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s);
+int max_block_tiles(const enkfmc_plan *p);
 hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const double *V, double *out,
                             hipStream_t s);
 hipError_t launch_analysis_dual(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld,

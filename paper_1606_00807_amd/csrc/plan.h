@@ -41,7 +41,7 @@ struct Layout {
   size_t blocks, fit_glob, fit_blk, fit_rows, row_ptr, col, csc_ptr, csc_row, csc_nz, interior_src, bobs_o, bobs_row;
   size_t g2f_ptr, g2f, o2b_ptr, o2b, bobs_fit, ot_jmax;
   size_t rt_ptr, rt_col, rt_slot, ct_ptr, ct_row, ct_slot;
-  size_t tval, dvec, mean, U, Z, F, S, Q, P, W, aux1, aux2, aux3, dbar, red, tiles, tinv, status;
+  size_t tval, dvec, mean, U, Z, F, S, Q, P, W, aux1, aux2, aux3, dbar, red, tiles, tinv, tdiag, status;
   size_t total;
 };
 
