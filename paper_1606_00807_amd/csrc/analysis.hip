@@ -29,18 +29,20 @@ __device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_
 
 // Dense tiles T_RC (row-major) of row tile R, and the inverse of T_RR.
 // One wavefront per (block, row tile).  Each lane fills whole tile rows: for
-// (row i, column tile C) it finds the entries of row i with columns in
-// [16C, 16C + 16) (contiguous, as a row's predecessors are ascending) and writes
-// the 16 values, zeros included.  The diagonal tile also goes to LDS, where 16
-// lanes invert it.
+// (row i, column tile C) the row's entries in [16C, 16C + 16) start at the
+// planned offset and end where the next tile's begin; they are scattered into
+// a zeroed row of the lane's LDS and written out as 16 values.  The diagonal
+// tile also goes to LDS, where 16 lanes invert it.
 __global__ __launch_bounds__(64) void k_build_tiles(const Block *__restrict__ blocks,
                                                     const int64_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ col, const double *__restrict__ tval,
                                                     const int64_t *__restrict__ rt_ptr,
                                                     const int32_t *__restrict__ rt_col,
-                                                    const int32_t *__restrict__ rt_slot, double *__restrict__ tiles,
+                                                    const int32_t *__restrict__ rt_slot,
+                                                    const uint16_t *__restrict__ teoff, double *__restrict__ tiles,
                                                     double *__restrict__ tinv, double *__restrict__ tdiag) {
   __shared__ double diag[256];
+  __shared__ double srow[64 * 17];
   const Block B = blocks[blockIdx.x];
   const int R = blockIdx.y;
   if (R >= B.nrt) return;
@@ -52,26 +54,22 @@ __global__ __launch_bounds__(64) void k_build_tiles(const Block *__restrict__ bl
     const int i = pr & 15, t = pr >> 4;          // t == nt: the diagonal tile
     const int C = t < nt ? rt_col[t0 + t] : R;
     const int row = 16 * R + i;
-    double v[16];
+    double *sr = srow + lane * 17;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = 0.0;
+    for (int j = 0; j < 16; ++j) sr[j] = 0.0;
     if (row < B.n) {
-      const int64_t ka = row_ptr[B.row0 + row], kb = row_ptr[B.row0 + row + 1];
-      int64_t lo = ka, hi = kb;                  // first entry with col >= 16C
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (col[mid] < 16 * C) lo = mid + 1;
-        else hi = mid;
-      }
-      int64_t k = lo;
+      const int64_t ka = row_ptr[B.row0 + row];
+      const int64_t e0 = ka + teoff[16 * (t0 + rt + t) + i];
+      const int64_t e1 = t < nt ? ka + teoff[16 * (t0 + rt + t + 1) + i] : row_ptr[B.row0 + row + 1];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        if (k < kb && col[k] == 16 * C + j) {
-          v[j] = tval[k];
-          ++k;
-        }
+      for (int e = 0; e < 16; ++e) {
+        const int64_t k = e0 + e;
+        if (k < e1) sr[col[k] - 16 * C] = tval[k];
       }
     }
+    double v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = sr[j];
     double *dst = (t < nt ? tiles + (int64_t)rt_slot[t0 + t] * 256 : diag) + i * 16;
 #pragma unroll
     for (int j = 0; j < 16; j += 2) *(d2 *)(dst + j) = d2{v[j], v[j + 1]};
@@ -354,7 +352,8 @@ int max_block_tiles(const enkfmc_plan *p) {
 hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s) {
   phase_begin(p, ENKFMC_PH_TILES, s);
   hipLaunchKernelGGL(k_build_tiles, dim3((unsigned)p->blocks.size(), (unsigned)max_block_tiles(p)), dim3(64), 0, s,
-                     d.blocks, d.row_ptr, d.col, d.tval, d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tinv, d.tdiag);
+                     d.blocks, d.row_ptr, d.col, d.tval, d.rt_ptr, d.rt_col, d.rt_slot, d.tile_eoff, d.tiles, d.tinv,
+                     d.tdiag);
   phase_end(p, ENKFMC_PH_TILES, s);
   return hipGetLastError();
 }

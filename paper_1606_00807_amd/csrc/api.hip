@@ -145,6 +145,7 @@ enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes,
   HIPCHK(put(p, L.ct_ptr, p->ct_ptr, s), "set_workspace");
   HIPCHK(put(p, L.ct_row, p->ct_row, s), "set_workspace");
   HIPCHK(put(p, L.ct_slot, p->ct_slot, s), "set_workspace");
+  HIPCHK(put(p, L.tile_eoff, p->tile_eoff, s), "set_workspace");
   HIPCHK(hipStreamSynchronize(s), "set_workspace");
   return ENKFMC_OK;
 }

@@ -166,6 +166,7 @@ __global__ __launch_bounds__(64) void k_adj_factor_tiles(const Block *__restrict
                                                          const int64_t *__restrict__ rt_ptr,
                                                          const int32_t *__restrict__ rt_col,
                                                          const int32_t *__restrict__ rt_slot,
+                                                         const uint16_t *__restrict__ teoff,
                                                          const double *__restrict__ tiles,
                                                          const double *__restrict__ tdiag,
                                                          const double *__restrict__ dvec, const double *__restrict__ Z,
@@ -200,6 +201,7 @@ __global__ __launch_bounds__(64) void k_adj_factor_tiles(const Block *__restrict
       az[r] = in ? Zb[(int64_t)row * N + colj] : 0.0;
       aw[r] = in ? Wb[(int64_t)row * N + colj] : 0.0;
     }
+#pragma unroll 2
     for (int t = 0; t <= nt; ++t) {            // t == nt: the diagonal tile
       const int C = t < nt ? rt_col[t0 + t] : R;
       const double *Tt = t < nt ? tiles + (int64_t)rt_slot[t0 + t] * 256 : tdiag + rt * 256;
@@ -237,6 +239,7 @@ __global__ __launch_bounds__(64) void k_adj_factor_tiles(const Block *__restrict
     const int jr = 16 * C + c;                 // row of W_C, Z_C for the B operand
     const bool jin = jr < B.n;
     d4 o = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 5
     for (int ks = 0; 4 * ks < N; ++ks) {
       const int k = 4 * ks + q;
       const bool kin = k < N;
@@ -253,14 +256,14 @@ __global__ __launch_bounds__(64) void k_adj_factor_tiles(const Block *__restrict
     if (lane < 16) {
       const int row = 16 * R + lane;
       if (row < B.n) {
-        const int64_t ka = row_ptr[B.row0 + row], kb = row_ptr[B.row0 + row + 1];
-        int64_t lo = ka, hi = kb;              // first entry with col >= 16C
-        while (lo < hi) {
-          const int64_t mid = (lo + hi) >> 1;
-          if (col[mid] < 16 * C) lo = mid + 1;
-          else hi = mid;
+        const int64_t ka = row_ptr[B.row0 + row];
+        const int64_t e0 = ka + teoff[16 * (t0 + rt + t) + lane];
+        const int64_t e1 = t < nt ? ka + teoff[16 * (t0 + rt + t + 1) + lane] : row_ptr[B.row0 + row + 1];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int64_t k = e0 + e;
+          if (k < e1) bbar[k] = sout[lane * 17 + col[k] - 16 * C];
         }
-        for (int64_t k = lo; k < kb && col[k] < 16 * C + 16; ++k) bbar[k] = sout[lane * 17 + col[k] - 16 * C];
       }
     }
     wave_lds_sync();
@@ -446,18 +449,106 @@ size_t adj_regress_lds(const enkfmc_plan *p) {
   return (size_t)N * N * 8 + (size_t)(2 * vl + 2 * N + mp + 8) * 8 + (size_t)mp * 4 + 16;
 }
 
-// dX_b of every component: the direct term Gbar, plus the anomaly projection
-// of Ubar gathered over the fit rows of the component (sub-domain order) and
-// their successors (CSC order).  One wavefront per component, N <= 128.
-__global__ __launch_bounds__(256) void k_adj_gather(const Block *__restrict__ blocks,
-                                                    const int32_t *__restrict__ fit_blk,
-                                                    const int64_t *__restrict__ g2f_ptr,
-                                                    const int32_t *__restrict__ g2f,
-                                                    const int64_t *__restrict__ csc_ptr,
-                                                    const int32_t *__restrict__ csc_row,
-                                                    const int32_t *__restrict__ csc_nz,
-                                                    const double *__restrict__ tval, const double *__restrict__ sv,
-                                                    const double *__restrict__ e1, const double *__restrict__ e2,
+// Ubar of every fit row by 16-row column tiles: for column tile C of a block,
+//   Ubar_C = sum_R (S_RC^T E1_R - T_RC^T E2_R) - E2_C
+// over the pattern's tiles (R, C), the diagonal tile included (strictly lower
+// parts); S holds the rows' s in the pattern of T.  One wavefront per (block,
+// column tile); each S_RC is assembled in LDS from the CSR entries, T_RC comes
+// from the dense tiles.  LDS: 16 x 17 doubles.
+__global__ __launch_bounds__(64) void k_adj_ubar_tiles(const Block *__restrict__ blocks,
+                                                       const int64_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const int64_t *__restrict__ rt_ptr,
+                                                       const uint16_t *__restrict__ teoff,
+                                                       const int64_t *__restrict__ ct_ptr,
+                                                       const int32_t *__restrict__ ct_row,
+                                                       const int32_t *__restrict__ ct_slot,
+                                                       const double *__restrict__ tiles,
+                                                       const double *__restrict__ tdiag, const double *__restrict__ sv,
+                                                       const double *__restrict__ e1, const double *__restrict__ e2,
+                                                       int N, double *__restrict__ ubar) {
+  constexpr int kMaxCT = 8;                    // member tiles (N <= 128)
+  __shared__ double sS[16 * 17];
+  const Block B = blocks[blockIdx.x];
+  const int C = blockIdx.y;
+  if (C >= B.nrt) return;
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int nct = (N + 15) >> 4;
+  const double *E1 = e1 + B.row0 * N, *E2 = e2 + B.row0 * N;
+  d4 acc[kMaxCT];
+#pragma unroll
+  for (int cc = 0; cc < kMaxCT; ++cc) {
+    const int colj = 16 * cc + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * C + 4 * r + q;
+      acc[cc][r] = (cc < nct && colj < N && row < B.n) ? -E2[(int64_t)row * N + colj] : 0.0;
+    }
+  }
+  const int64_t s0 = ct_ptr[B.rt0 + C], s1 = ct_ptr[B.rt0 + C + 1];
+  for (int64_t t = s0; t <= s1; ++t) {         // t == s1: the diagonal tile (R = C)
+    const int R = t < s1 ? ct_row[t] : C;
+    const double *Tt = t < s1 ? tiles + (int64_t)ct_slot[t] * 256 : tdiag + (B.rt0 + C) * 256;
+    // S_RC: row i of R, columns [16C, 16C + 16); the row's entries of tile
+    // (R, C) start at the planned offset and end where the next tile's begin
+    if (lane < 16) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) sS[lane * 17 + j] = 0.0;
+      const int row = 16 * R + lane;
+      if (row < B.n) {
+        const int64_t rtR = B.rt0 + R;
+        const int64_t ix = 16 * ((t < s1 ? (int64_t)ct_slot[t] : rt_ptr[rtR + 1]) + rtR) + lane;
+        const int64_t ka = row_ptr[B.row0 + row];
+        const int64_t e0 = ka + teoff[ix];
+        const int64_t e1 = t < s1 ? ka + teoff[ix + 16] : row_ptr[B.row0 + row + 1];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int64_t k = e0 + e;
+          if (k < e1) sS[lane * 17 + col[k] - 16 * C] = sv[k];
+        }
+      }
+    }
+    wave_lds_sync();
+    // A operands: (S_RC^T)[c][k] = S_RC[k][c] and -(T_RC^T)[c][k], k = 4kc + q
+    double as[4], at[4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      as[kc] = sS[(4 * kc + q) * 17 + c];
+      at[kc] = -Tt[(4 * kc + q) * 16 + c];
+    }
+#pragma unroll
+    for (int cc = 0; cc < kMaxCT; ++cc) {
+      if (cc >= nct) break;
+      const int colj = 16 * cc + c;
+      const bool colok = colj < N;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        const int er = 16 * R + 4 * kc + q;
+        const bool in = er < B.n && colok;
+        acc[cc] = mfma64(as[kc], in ? E1[(int64_t)er * N + colj] : 0.0, acc[cc]);
+        acc[cc] = mfma64(at[kc], in ? E2[(int64_t)er * N + colj] : 0.0, acc[cc]);
+      }
+    }
+    wave_lds_sync();
+  }
+  double *Ub = ubar + B.row0 * N;
+#pragma unroll
+  for (int cc = 0; cc < kMaxCT; ++cc) {
+    const int colj = 16 * cc + c;
+    if (cc >= nct || colj >= N) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * C + 4 * r + q;
+      if (row < B.n) Ub[(int64_t)row * N + colj] = acc[cc][r];
+    }
+  }
+}
+
+// dX_b of every component: the direct term Gbar plus the anomaly projection of
+// Ubar summed over the component's fit rows in sub-domain order.  One
+// wavefront per component, N <= 128.
+__global__ __launch_bounds__(256) void k_adj_gather(const int64_t *__restrict__ g2f_ptr,
+                                                    const int32_t *__restrict__ g2f, const double *__restrict__ ubar,
                                                     const double *__restrict__ dXa, int64_t n, int N,
                                                     double *__restrict__ dXb) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -466,21 +557,10 @@ __global__ __launch_bounds__(256) void k_adj_gather(const Block *__restrict__ bl
   double ub[2] = {0.0, 0.0};
   for (int64_t t = g2f_ptr[j]; t < g2f_ptr[j + 1]; ++t) {
     const int64_t f = g2f[t];
-    const Block B = blocks[fit_blk[f]];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int cc = lane + 64 * h;
-      if (cc < N) ub[h] -= e2[f * N + cc];
-    }
-    for (int64_t sl = csc_ptr[f]; sl < csc_ptr[f + 1]; ++sl) {
-      const int64_t i = B.row0 + csc_row[sl];
-      const int64_t k = B.nz0 + csc_nz[sl];
-      const double s = sv[k], tv = tval[k];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int cc = lane + 64 * h;
-        if (cc < N) ub[h] += s * e1[i * N + cc] - tv * e2[i * N + cc];
-      }
+      if (cc < N) ub[h] += ubar[f * N + cc];
     }
   }
   const double mean = wave_sum(ub[0] + ub[1]) / N;
@@ -572,8 +652,8 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
     e = hipFuncSetAttribute((const void *)k_adj_factor_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_adj_factor_tiles, dim3(nb, (unsigned)max_block_tiles(p)), dim3(64), lds, s, d.blocks,
-                       d.row_ptr, d.col, d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tdiag, d.dvec, d.Z, d.W, N, d.dbar,
-                       d.aux3);
+                       d.row_ptr, d.col, d.rt_ptr, d.rt_col, d.rt_slot, d.tile_eoff, d.tiles, d.tdiag, d.dvec, d.Z, d.W,
+                       N, d.dbar, d.aux3);
   }
   phase_end(p, ENKFMC_PH_ADJ_FACTOR, s);
   phase_begin(p, ENKFMC_PH_ADJ_REGRESS, s);
@@ -588,8 +668,11 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   }
   phase_end(p, ENKFMC_PH_ADJ_REGRESS, s);
   phase_begin(p, ENKFMC_PH_ADJ_GATHER, s);
-  hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)((p->n + 3) / 4)), dim3(256), 0, s, d.blocks, d.fit_blk, d.g2f_ptr,
-                     d.g2f, d.csc_ptr, d.csc_row, d.csc_nz, d.tval, d.aux3, d.aux1, d.aux2, dXa, p->n, N, dXb);
+  hipLaunchKernelGGL(k_adj_ubar_tiles, dim3(nb, (unsigned)max_block_tiles(p)), dim3(64), 0, s, d.blocks, d.row_ptr,
+                     d.col, d.rt_ptr, d.tile_eoff, d.ct_ptr, d.ct_row, d.ct_slot, d.tiles, d.tdiag, d.aux3, d.aux1,
+                     d.aux2, N, d.ubar);
+  hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)((p->n + 3) / 4)), dim3(256), 0, s, d.g2f_ptr, d.g2f, d.ubar, dXa,
+                     p->n, N, dXb);
   if (p->m > 0)
     hipLaunchKernelGGL(k_adj_obs<TX>, dim3((unsigned)((p->m + 3) / 4)), dim3(256), 0, s, d.o2b_ptr, d.o2b,
                        d.bobs_fit, d.fit_glob, d.Z, d.W, Y, Xb, ld, r_diag, p->m, N, dXb, dlogR);

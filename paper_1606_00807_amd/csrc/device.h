@@ -21,7 +21,8 @@ struct Dev {
   const int32_t *o2b, *bobs_fit, *ot_jmax;
   const int64_t *rt_ptr, *ct_ptr;
   const int32_t *rt_col, *rt_slot, *ct_row, *ct_slot;
-  double *tiles, *tinv, *tdiag;
+  const uint16_t *tile_eoff;
+  double *tiles, *tinv, *tdiag, *ubar;
   double *tval, *dvec, *mean, *U, *Z, *F, *S, *Q, *P, *W, *aux1, *aux2, *aux3, *dbar, *red;
   int32_t *status;
 };
@@ -54,9 +55,11 @@ inline Dev make_dev(enkfmc_plan *p) {
   d.ct_ptr = (const int64_t *)(w + L.ct_ptr);
   d.ct_row = (const int32_t *)(w + L.ct_row);
   d.ct_slot = (const int32_t *)(w + L.ct_slot);
+  d.tile_eoff = (const uint16_t *)(w + L.tile_eoff);
   d.tiles = (double *)(w + L.tiles);
   d.tinv = (double *)(w + L.tinv);
   d.tdiag = (double *)(w + L.tdiag);
+  d.ubar = (double *)(w + L.ubar);
   d.tval = (double *)(w + L.tval);
   d.dvec = (double *)(w + L.dvec);
   d.mean = (double *)(w + L.mean);

@@ -251,6 +251,33 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
     }
   }
   if (p->n_slots >= (int64_t(1) << 31)) { *err = "too many tiles"; return ENKFMC_EUNSUPPORTED; }
+  if (p->max_p > 65535) { *err = "too many predecessors"; return ENKFMC_EUNSUPPORTED; }
+  p->tile_eoff.assign((size_t)16 * (p->n_slots + p->n_rt), 0);
+  for (const Block &B : p->blocks)
+    for (int32_t R = 0; R < B.nrt; ++R) {
+      const int64_t rt = B.rt0 + R, t0 = p->rt_ptr[rt];
+      const int32_t nt = (int32_t)(p->rt_ptr[rt + 1] - t0);
+      for (int32_t i = 0; i < 16 && 16 * R + i < B.n; ++i) {
+        const int64_t ka = p->row_ptr[B.row0 + 16 * R + i], kb = p->row_ptr[B.row0 + 16 * R + i + 1];
+        for (int32_t t = 0; t <= nt; ++t) {
+          const int32_t C = t < nt ? p->rt_col[t0 + t] : R;
+          int64_t k = ka;
+          while (k < kb && p->col[k] < 16 * C) ++k;
+          p->tile_eoff[(size_t)16 * (t0 + rt + t) + i] = (uint16_t)(k - ka);
+        }
+        // the kernels rely on: tile t's entries are exactly those up to the
+        // next tile's offset, at most 16 of them, all in columns [16C, 16C + 16)
+        for (int32_t t = 0; t <= nt; ++t) {
+          const int32_t C = t < nt ? p->rt_col[t0 + t] : R;
+          const int64_t e0 = ka + p->tile_eoff[(size_t)16 * (t0 + rt + t) + i];
+          const int64_t e1 = t < nt ? ka + p->tile_eoff[(size_t)16 * (t0 + rt + t + 1) + i] : kb;
+          if (e1 < e0 || e1 - e0 > 16) { *err = "internal: tile entry ranges"; return ENKFMC_EINVAL; }
+          for (int64_t k = e0; k < e1; ++k)
+            if (p->col[k] < 16 * C || p->col[k] >= 16 * C + 16) { *err = "internal: tile entry ranges"; return ENKFMC_EINVAL; }
+        }
+        if (p->tile_eoff[(size_t)16 * (t0 + rt) + i] != 0) { *err = "internal: tile entry ranges"; return ENKFMC_EINVAL; }
+      }
+    }
   // transposed tile lists: for every column tile, the later row tiles (ascending)
   p->ct_ptr.assign(p->n_rt + 1, 0);
   for (const Block &B : p->blocks)
@@ -303,6 +330,7 @@ void compute_layout(enkfmc_plan *p) {
   L.ct_ptr = take((size_t)(p->n_rt + 1) * 8);
   L.ct_row = take(p->ct_row.size() * 4);
   L.ct_slot = take(p->ct_slot.size() * 4);
+  L.tile_eoff = take(p->tile_eoff.size() * 2);
   L.tval = take(nz * 8);
   L.dvec = take(nf * 8);
   L.mean = take(n * 8);
@@ -321,6 +349,7 @@ void compute_layout(enkfmc_plan *p) {
   L.tiles = take((size_t)p->n_slots * 256 * 8);
   L.tinv = take((size_t)p->n_rt * 256 * 8);
   L.tdiag = take((size_t)p->n_rt * 256 * 8);
+  L.ubar = take(nf * N * 8);
   L.status = take(64);
   L.total = off;
 }
