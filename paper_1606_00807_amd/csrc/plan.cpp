@@ -259,9 +259,9 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
       const int32_t nt = (int32_t)(p->rt_ptr[rt + 1] - t0);
       for (int32_t i = 0; i < 16 && 16 * R + i < B.n; ++i) {
         const int64_t ka = p->row_ptr[B.row0 + 16 * R + i], kb = p->row_ptr[B.row0 + 16 * R + i + 1];
+        int64_t k = ka;                          // tiles ascending: one pass over the row
         for (int32_t t = 0; t <= nt; ++t) {
           const int32_t C = t < nt ? p->rt_col[t0 + t] : R;
-          int64_t k = ka;
           while (k < kb && p->col[k] < 16 * C) ++k;
           p->tile_eoff[(size_t)16 * (t0 + rt + t) + i] = (uint16_t)(k - ka);
         }
