@@ -86,6 +86,26 @@ __device__ inline double rsqrt_nr(double x) {
 template <int T>
 __device__ __forceinline__ constexpr int tix(int I, int J) { return I * (I + 1) / 2 + J; }
 
+// Data-parallel-primitive move of a double within rows of 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over each row of 16 lanes, every lane of the row getting the same value:
+// partners i^1 and i^2 inside quads, then the mirrored lane in each half row
+// and in the row (each pairs lanes that already hold equal partial sums).
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);   // row_half_mirror
+  v += dpp_d<0x140>(v);   // row_mirror
+  return v;
+}
+
 // Arrays of the adjoint pass.
 struct AdjIO {
   const double *dbar;   // dL/dd per fit row
@@ -146,10 +166,7 @@ __device__ __forceinline__ void adj_rhs(const int lane, const int64_t r, const i
 #pragma unroll
     for (int I = 0; I < kMaxT; ++I)
       if (I < TN) sm = fma(U[off + 16 * I], ev[I], sm);
-    sm += __shfl_xor(sm, 8, 16);
-    sm += __shfl_xor(sm, 4, 16);
-    sm += __shfl_xor(sm, 2, 16);
-    sm += __shfl_xor(sm, 1, 16);
+    sm = row16_sum(sm);
     if (c == 0 && a < p) {
       const double b = adj.sb[lo + a] - sm;
       adj.sb[lo + a] = b;
@@ -452,10 +469,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       double b = 0.0;
 #pragma unroll
       for (int I = 0; I < T; ++I) b = fma(U[off + 16 * I], wv[I], b);
-      b += __shfl_xor(b, 8, 16);
-      b += __shfl_xor(b, 4, 16);
-      b += __shfl_xor(b, 2, 16);
-      b += __shfl_xor(b, 1, 16);
+      b = row16_sum(b);
       if (c == 0 && a < p) tval[lo + a] = -b;
     }
     if (q == 0) {
@@ -511,10 +525,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         double b = 0.0;
 #pragma unroll
         for (int I = 0; I < T; ++I) b = fma(U[off + 16 * I], wv[I], b);
-        b += __shfl_xor(b, 8, 16);
-        b += __shfl_xor(b, 4, 16);
-        b += __shfl_xor(b, 2, 16);
-        b += __shfl_xor(b, 1, 16);
+        b = row16_sum(b);
         if (c == 0 && a < p) {
           const double sv = (nm1 / mu) * (adj.sb[lo + a] - b);
           sl[a] = sv;
