@@ -121,15 +121,32 @@ __global__ __launch_bounds__(64) void k_bwd_sweep(const Block *__restrict__ bloc
     d4 acc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = (16 * C + 4 * r + q == jo) ? 1.0 : 0.0;
-    const int64_t s0 = ct_ptr[B.rt0 + C], s1 = ct_ptr[B.rt0 + C + 1];
-    for (int64_t t = s0; t < s1; ++t) {
-      const int R = ct_row[t];
-      if (R > Cs) continue;   // zero tile of F
+    // later row tiles R > Cs hold zeros of F; ascending, so they end the list.
+    // The loads of tile t + 1 are issued before the MFMAs of tile t.
+    const int64_t s0 = ct_ptr[B.rt0 + C];
+    int64_t s1 = ct_ptr[B.rt0 + C + 1];
+    while (s1 > s0 && ct_row[s1 - 1] > Cs) --s1;
+    double ta[4], fa[4];
+    auto load = [&](int64_t t, double (&tv)[4], double (&fv)[4]) {
       const double *Tt = tiles + (int64_t)ct_slot[t] * 256;
-      const double *Fr = Fb + (int64_t)(16 * R) * ldf + 16 * oc + c;
+      const double *Fr = Fb + (int64_t)(16 * ct_row[t]) * ldf + 16 * oc + c;
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc)
-        acc = mfma64(-Tt[(4 * kc + q) * 16 + c], Fr[(int64_t)(4 * kc + q) * ldf], acc);
+      for (int kc = 0; kc < 4; ++kc) {
+        tv[kc] = Tt[(4 * kc + q) * 16 + c];
+        fv[kc] = Fr[(int64_t)(4 * kc + q) * ldf];
+      }
+    };
+    if (s0 < s1) load(s0, ta, fa);
+    for (int64_t t = s0; t < s1; ++t) {
+      double tb[4] = {0.0, 0.0, 0.0, 0.0}, fb[4] = {0.0, 0.0, 0.0, 0.0};
+      if (t + 1 < s1) load(t + 1, tb, fb);
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) acc = mfma64(-ta[kc], fa[kc], acc);
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        ta[kc] = tb[kc];
+        fa[kc] = fb[kc];
+      }
     }
     const double *Ti = tinv + (B.rt0 + C) * 256;
     d4 out = d4{0.0, 0.0, 0.0, 0.0};
