@@ -154,42 +154,59 @@ __device__ __forceinline__ void adj_rhs(const int lane, const int64_t r, const i
   wave_lds_sync();
   // b_a = betabar_a - sum_k U[P_a][k] epsbar_k: lane (q, c) loads members
   // 16I + c of predecessor 4ks + q and the 16 lanes of each quarter add up.
+  // The kernel form accumulates (U_P^T b)_k from the same fragments.
   const int TN = (N + 15) >> 4;
   double ev[kMaxT];
 #pragma unroll
   for (int I = 0; I < kMaxT; ++I) ev[I] = I < TN ? el[16 * I + c] : 0.0;
   const int ksteps = (p + 3) >> 2;
-  for (int ks = 0; ks < ksteps; ++ks) {
-    const int a = 4 * ks + q;
-    const int off = L.pidx[a] * ldu + c;
-    double sm = 0.0;
+  if constexpr (KF) {
+    double tacc[T];
 #pragma unroll
-    for (int I = 0; I < kMaxT; ++I)
-      if (I < TN) sm = fma(U[off + 16 * I], ev[I], sm);
-    sm = row16_sum(sm);
-    if (c == 0 && a < p) {
-      const double b = adj.sb[lo + a] - sm;
-      adj.sb[lo + a] = b;
-      bl[a] = b;
+    for (int I = 0; I < T; ++I) tacc[I] = 0.0;
+    for (int ks = 0; ks < ksteps; ++ks) {
+      const int a = 4 * ks + q;
+      const int off = L.pidx[a] * ldu + c;
+      double f[T], sm = 0.0;
+#pragma unroll
+      for (int I = 0; I < T; ++I) {
+        f[I] = U[off + 16 * I];
+        sm = fma(f[I], ev[I], sm);
+      }
+      sm = row16_sum(sm);
+      const double b = a < p ? adj.sb[lo + a] - sm : 0.0;
+      if (c == 0 && a < p) adj.sb[lo + a] = b;
+#pragma unroll
+      for (int I = 0; I < T; ++I) tacc[I] = fma(f[I], b, tacc[I]);
     }
-  }
-  // entries a >= p of bl still hold the zero padding written above
-  wave_lds_sync();
-  if constexpr (!KF) {
+#pragma unroll
+    for (int I = 0; I < T; ++I) {
+      double e = tacc[I];
+      e += __shfl_xor(e, 16, 64);
+      e += __shfl_xor(e, 32, 64);
+      augv[I] = (q == 0 && 16 * I + c < N) ? e : 0.0;
+    }
+  } else {
+    for (int ks = 0; ks < ksteps; ++ks) {
+      const int a = 4 * ks + q;
+      const int off = L.pidx[a] * ldu + c;
+      double sm = 0.0;
+#pragma unroll
+      for (int I = 0; I < kMaxT; ++I)
+        if (I < TN) sm = fma(U[off + 16 * I], ev[I], sm);
+      sm = row16_sum(sm);
+      if (c == 0 && a < p) {
+        const double b = adj.sb[lo + a] - sm;
+        adj.sb[lo + a] = b;
+        bl[a] = b;
+      }
+    }
+    // entries a >= p of bl still hold the zero padding written above
+    wave_lds_sync();
 #pragma unroll
     for (int g = 0; g < T; ++g) {   // p <= 16 T
       const int a = 16 * g + c;
       augv[g] = (q == 0 && a < p) ? bl[a] : 0.0;
-    }
-  } else {
-#pragma unroll
-    for (int I = 0; I < T; ++I) {     // (U_P^T b)_k, members k = 16I + c
-      const int k = 16 * I + c;
-      double e = 0.0;
-      for (int a = q; a < p; a += 4) e = fma(bl[a], U[L.pidx[a] * ldu + k], e);
-      e += __shfl_xor(e, 16, 64);
-      e += __shfl_xor(e, 32, 64);
-      augv[I] = (q == 0 && k < N) ? e : 0.0;
     }
   }
   wave_lds_sync();
@@ -511,30 +528,46 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   } else {
     // ---- 5'. adjoint: s, dL/dlam, e2 ------------------------------------------
     const double nm1 = (double)(N - 1);
-    double *sl = L.tile;     // s (kMaxP entries)
     double ls = 0.0;
     if (KF) {
-      // s_a = (N-1)/mu (b_a - sum_k U[P_a][k] x_k), lanes as for beta above
-      double wv[T];
+      // s_a = (N-1)/mu (b_a - sum_k U[P_a][k] x_k) and g = U_P^T s from the same
+      // fragments (lanes as for beta above); e2 = -(g/(N-1) + epsbar)
+      double wv[T], gacc[T];
 #pragma unroll
-      for (int I = 0; I < T; ++I) wv[I] = y[16 * I + c];
+      for (int I = 0; I < T; ++I) {
+        wv[I] = y[16 * I + c];
+        gacc[I] = 0.0;
+      }
       const int ksteps = (p + 3) >> 2;
       for (int ks = 0; ks < ksteps; ++ks) {
         const int a = 4 * ks + q;
         const int off = L.pidx[a] * ldu + c;
-        double b = 0.0;
+        double f[T], b = 0.0;
 #pragma unroll
-        for (int I = 0; I < T; ++I) b = fma(U[off + 16 * I], wv[I], b);
+        for (int I = 0; I < T; ++I) {
+          f[I] = U[off + 16 * I];
+          b = fma(f[I], wv[I], b);
+        }
         b = row16_sum(b);
+        const double sv = a < p ? (nm1 / mu) * (adj.sb[lo + a] - b) : 0.0;
         if (c == 0 && a < p) {
-          const double sv = (nm1 / mu) * (adj.sb[lo + a] - b);
-          sl[a] = sv;
           adj.sb[lo + a] = sv;
           ls = fma(sv, tval[lo + a], ls);
         }
+#pragma unroll
+        for (int I = 0; I < T; ++I) gacc[I] = fma(f[I], sv, gacc[I]);
+      }
+#pragma unroll
+      for (int I = 0; I < T; ++I) {
+        double e = gacc[I];
+        e += __shfl_xor(e, 16, 64);
+        e += __shfl_xor(e, 32, 64);
+        const int k = 16 * I + c;
+        if (q == 0 && k < N) adj.e2[r * N + k] = -(e / nm1 + adj.e2[r * N + k]);
       }
     } else {
       // same lane per entry as the pre-pass, which stored b there
+      double *sl = L.tile;     // s (kMaxP entries)
       for (int ks = 0; 4 * ks < p; ++ks) {
         const int a = 4 * ks + q;
         if (c == 0 && a < p) {
@@ -544,18 +577,18 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
           ls = fma(sv, tval[lo + a], ls);
         }
       }
-    }
-    wave_lds_sync();
-    // e2 = -(U_P^T s/(N-1) + epsbar), epsbar left in e2 by the pre-pass
+      wave_lds_sync();
+      // e2 = -(U_P^T s/(N-1) + epsbar), epsbar left in e2 by the pre-pass
 #pragma unroll
-    for (int I = 0; I < kMaxT; ++I) {
-      if (16 * I >= N) break;
-      const int k = 16 * I + c;
-      double e = 0.0;
-      for (int a = q; a < p; a += 4) e = fma(sl[a], U[L.pidx[a] * ldu + k], e);
-      e += __shfl_xor(e, 16, 64);
-      e += __shfl_xor(e, 32, 64);
-      if (q == 0 && k < N) adj.e2[r * N + k] = -(e / nm1 + adj.e2[r * N + k]);
+      for (int I = 0; I < kMaxT; ++I) {
+        if (16 * I >= N) break;
+        const int k = 16 * I + c;
+        double e = 0.0;
+        for (int a = q; a < p; a += 4) e = fma(sl[a], U[L.pidx[a] * ldu + k], e);
+        e += __shfl_xor(e, 16, 64);
+        e += __shfl_xor(e, 32, 64);
+        if (q == 0 && k < N) adj.e2[r * N + k] = -(e / nm1 + adj.e2[r * N + k]);
+      }
     }
     ls = wave_sum(ls);
     if (lane == 0) adj.lam_row[r] = ls;
