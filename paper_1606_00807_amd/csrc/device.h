@@ -80,6 +80,17 @@ inline Dev make_dev(enkfmc_plan *p) {
 }
 
 // First error wins; status[1] records where it happened.
+// MI355X dispatches the workgroups of a launch to its 8 XCDs in turn
+// (workgroup b to XCD b mod 8), and each XCD has an L2 of its own.  This maps
+// b to a logical index such that every XCD runs one contiguous range of
+// logical workgroups (a bijection on [0, G)): neighbouring rows, which share
+// most of their predecessors' rows of U, then meet in the same L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G) {
+  const int64_t x = b % kXcds, s = b / kXcds, q = G / kXcds, rm = G % kXcds;
+  return x < rm ? x * (q + 1) + s : rm * (q + 1) + (x - rm) * q + s;
+}
+
 __device__ inline void set_error(int32_t *status, int32_t code, int32_t where) {
   if (atomicCAS(status, 0, code) == 0) atomicExch(status + 1, where);
 }

@@ -606,7 +606,7 @@ __global__ __launch_bounds__(256, occupancy_for(T, KF)) void k_fit_batched(
     double *__restrict__ dvec, int32_t *status) {
   __shared__ WaveLds<T> lds[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t idx = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
   if (idx >= nrows) return;
   const int64_t r = rows[idx];
   WaveLds<T> &L = lds[wave];
@@ -636,7 +636,7 @@ __global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_b
     AdjIO adj, int32_t *status) {
   __shared__ WaveLds<T> lds[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t idx = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
   if (idx >= nrows) return;
   const int64_t r = rows[idx];
   WaveLds<T> &L = lds[wave];
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(256) void k_adj_p0(const int32_t *__restrict__ fit_
                                                 int ldu, int N, const int32_t *__restrict__ rows, int64_t nrows,
                                                 AdjIO adj) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t idx = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
   if (idx >= nrows) return;
   const int64_t r = rows[idx];
   const double *u = U + (int64_t)fit_glob[r] * ldu;
@@ -671,7 +671,7 @@ __global__ __launch_bounds__(256) void k_fit_p0(const int32_t *__restrict__ fit_
                                                 int ldu, int N, const int32_t *__restrict__ rows, int64_t nrows,
                                                 double *__restrict__ dvec, int32_t *status) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t idx = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
   if (idx >= nrows) return;
   const int64_t r = rows[idx];
   const double *u = U + (int64_t)fit_glob[r] * ldu;
