@@ -143,6 +143,34 @@ enkfmc_status enkfmc_analyze_backward(enkfmc_plan *p, const void *Xb, int32_t dt
                                       const double *r_diag, const double *dXa, double *dXb, double *dlogR,
                                       double *dridge, void *stream);
 
+/* Perturbed observations of one assimilation time (Alg. 1, its
+ * create_perturbed_observations step; Section 2.3 after eq. 11: the columns
+ * of Y^s carry data errors drawn from N(0, R), not re-centred).
+ * y: dev (m) float64 observations; r_diag: dev (m) float64 > 0;
+ * Ys: dev (m x N) float64, overwritten with
+ *   Ys[o][k] = y[o] + sqrt(r_diag[o]) * xi(seed, cycle, o, k).
+ * xi is standard normal: the Philox4x64-10 block (Salmon et al., SC'11) with
+ * key (seed, 0) and counter (k / 4, o, cycle, 0) gives four 64-bit words
+ * w_0..w_3; u_i = ((w_i >> 12) + 1/2) * 2^-52; Box-Muller maps (u_0, u_1) to
+ * members 4j, 4j+1 and (u_2, u_3) to 4j+2, 4j+3 (j = k / 4):
+ *   z = sqrt(-2 ln u_0) cos(2 pi u_1), z' = sqrt(-2 ln u_0) sin(2 pi u_1).
+ * A draw depends only on (seed, cycle, o, k).  Ys must not be the Y of an
+ * analysis whose enkfmc_analyze_backward is still to come.
+ * Errors: EINVAL (NULL argument), ESTATE (no workspace), EHIP. */
+enkfmc_status enkfmc_perturb_observations(enkfmc_plan *p, const double *y, const double *r_diag, uint64_t seed,
+                                          uint64_t cycle, double *Ys, void *stream);
+
+/* Squared error of the analysis mean at one assimilation time, the summand
+ * of the RMSE of eq. (18) (Section 4):
+ *   err[0] = sum_g (mean_k Xa[g][k] - x_ref[g])^2.
+ * Xa: dev (n x N), element type dtype, row stride ld >= N; x_ref: dev (n)
+ * float64; err: dev (1) float64, overwritten.  The sums run in a fixed order,
+ * so the result is bitwise repeatable.  Uses the workspace as scratch but
+ * leaves the state of fit and analysis as it was.
+ * Errors: EINVAL, ESTATE (no workspace), EHIP. */
+enkfmc_status enkfmc_analysis_sq_error(enkfmc_plan *p, const void *Xa, int32_t dtype, int64_t ld,
+                                       const double *x_ref, double *err, void *stream);
+
 /* Parity exports of sub-domain k (host copies, local numbering of Section 3).
  * Sizes first, then the arrays (any pointer may be NULL to skip it):
  *  loc2glob[n_sd]   global component of each local row

@@ -17,10 +17,12 @@ analysis  local primal analysis solved directly (eq. 11 per sub-domain, eq. 14,
           dual form (eqs. 12-13) as an independent cross-check.
 adjoint   reverse-mode derivative of fit + analysis with respect to X_b,
           log diag(R) and the ridge parameter.
+cycling   perturbed observations (Section 2.3, Alg. 1) from a counter-based
+          generator, the cycle loop of Alg. 1 and the RMSE of eq. (18).
 
 Every floating-point computation is in float64.  Readings of points where the
 paper is silent or ambiguous are listed in the module docstrings (R1..R14).
 """
 
-from . import geometry, fit, analysis, adjoint  # noqa: F401
+from . import geometry, fit, analysis, adjoint, cycling  # noqa: F401
 from .errors import OracleError  # noqa: F401

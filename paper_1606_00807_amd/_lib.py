@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_uint8, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_uint8, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libenkfmc.so")
@@ -54,6 +54,9 @@ SIGNATURES = {
                                  c_int32, c_void_p]),
     "enkfmc_analyze_backward": (c_int32, [c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_void_p,
                                           c_void_p, c_void_p, c_void_p, c_void_p]),
+    "enkfmc_perturb_observations": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_uint64, c_void_p,
+                                              c_void_p]),
+    "enkfmc_analysis_sq_error": (c_int32, [c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_void_p]),
     "enkfmc_get_pattern_sizes": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_int64),
                                            POINTER(c_int64)]),
     "enkfmc_get_pattern": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_uint8), POINTER(c_int64),

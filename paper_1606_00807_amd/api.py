@@ -179,6 +179,40 @@ class Plan:
                                                ctypes.c_void_p(dridge.data_ptr()), self._stream()))
         return dXb, dlogR[:self.m], dridge[0]
 
+    def perturb_observations(self, y, r_diag, seed: int, cycle: int, out=None):
+        """Y^s = y 1^T + E of one assimilation time (Alg. 1), E drawn on the
+        device from N(0, R) by the counter-based generator of
+        include/enkfmc.h.  Returns (m, N) float64 (`out` if given)."""
+        import torch
+        if self.m == 0:
+            return torch.empty((0, self.N), dtype=torch.float64, device="cuda")
+        self.ensure_workspace()
+        yv = self._dev64(y, (self.m,), "y")
+        r = self._dev64(r_diag, (self.m,), "r_diag")
+        if out is None:
+            out = torch.empty((max(self.m, 1), self.N), dtype=torch.float64, device="cuda")
+        elif (out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous()
+              or out.numel() < self.m * self.N):
+            raise ValueError("out must be a contiguous float64 CUDA tensor of m x N elements")
+        check(self.lib.enkfmc_perturb_observations(self._h, ctypes.c_void_p(yv.data_ptr()),
+                                                   ctypes.c_void_p(r.data_ptr()), int(seed) & (2**64 - 1),
+                                                   int(cycle) & (2**64 - 1), ctypes.c_void_p(out.data_ptr()),
+                                                   self._stream()))
+        return out[:self.m] if out.dim() == 2 else out
+
+    def analysis_sq_error(self, Xa, x_ref):
+        """sum_g (mean_k X_a[g, k] - x_ref[g])^2 (the summand of eq. 18), as a
+        (1,) float64 device tensor."""
+        import torch
+        self.ensure_workspace()
+        self._check_xb(Xa)
+        p, dt, ld = self._xb_args(Xa)
+        xr = self._dev64(x_ref, (self.n,), "x_ref")
+        err = torch.empty((1,), dtype=torch.float64, device="cuda")
+        check(self.lib.enkfmc_analysis_sq_error(self._h, p, dt, ld, ctypes.c_void_p(xr.data_ptr()),
+                                                ctypes.c_void_p(err.data_ptr()), self._stream()))
+        return err
+
     def factors(self, k: int):
         n_sd, nnz, _ = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         check(self.lib.enkfmc_get_pattern_sizes(self._h, int(k), ctypes.byref(n_sd), ctypes.byref(nnz), None))

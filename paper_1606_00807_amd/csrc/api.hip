@@ -221,6 +221,29 @@ enkfmc_status enkfmc_analyze_backward(enkfmc_plan *p, const void *Xb, int32_t dt
   return finish(p, s, "analyze_backward");
 }
 
+enkfmc_status enkfmc_perturb_observations(enkfmc_plan *p, const double *y, const double *r_diag, uint64_t seed,
+                                          uint64_t cycle, double *Ys, void *stream) {
+  if (!p || (p->m > 0 && (!y || !r_diag || !Ys))) return fail(ENKFMC_EINVAL, "perturb_observations: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  enkfmc_status st = begin(p, s, "perturb_observations");
+  if (st != ENKFMC_OK) return st;
+  HIPCHK(launch_perturb(y, r_diag, p->m, p->N, seed, cycle, Ys, s), "perturb_observations: launch");
+  return finish(p, s, "perturb_observations");
+}
+
+enkfmc_status enkfmc_analysis_sq_error(enkfmc_plan *p, const void *Xa, int32_t dtype, int64_t ld,
+                                       const double *x_ref, double *err, void *stream) {
+  if (!p || !Xa || !x_ref || !err) return fail(ENKFMC_EINVAL, "analysis_sq_error: NULL argument");
+  if (dtype != ENKFMC_F32 && dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "analysis_sq_error: bad dtype");
+  if (ld < p->N) return fail(ENKFMC_EINVAL, "analysis_sq_error: ld < N");
+  hipStream_t s = (hipStream_t)stream;
+  enkfmc_status st = begin(p, s, "analysis_sq_error");
+  if (st != ENKFMC_OK) return st;
+  const Dev d = make_dev(p);
+  HIPCHK(launch_sq_error(Xa, dtype, ld, p->n, p->N, x_ref, d.dbar, err, s), "analysis_sq_error: launch");
+  return finish(p, s, "analysis_sq_error");
+}
+
 enkfmc_status enkfmc_get_pattern_sizes(const enkfmc_plan *p, int32_t k, int64_t *n_sd, int64_t *nnz_sd,
                                        int64_t *m_sd) {
   if (!p || k < 0 || k >= (int32_t)p->subs.size()) return fail(ENKFMC_EINVAL, "get_pattern_sizes: bad sub-domain");

@@ -189,5 +189,12 @@ hipError_t launch_adj_regress_batched(enkfmc_plan *p, const Dev &d, double lam, 
 hipError_t launch_backward(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, const double *Y,
                            const double *r_diag, double lam, const double *dXa, double *dXb, double *dlogR,
                            double *dridge, hipStream_t s);
+hipError_t launch_perturb(const double *y, const double *r_diag, int64_t m, int N, uint64_t seed, uint64_t cycle,
+                          double *Ys, hipStream_t s);
+// Workgroups of the first level of the squared-error reduction; its partials
+// need that many doubles of scratch.
+constexpr int kSqErrorParts = 256;
+hipError_t launch_sq_error(const void *Xa, int32_t dtype, int64_t ld, int64_t n, int N, const double *xref,
+                           double *part, double *out, hipStream_t s);
 
 }  // namespace enkfmc

@@ -344,7 +344,7 @@ void compute_layout(enkfmc_plan *p) {
   L.aux1 = take(nf * N * 8);
   L.aux2 = take(nf * N * 8);
   L.aux3 = take(nz * 8);
-  L.dbar = take(std::max<size_t>(nf, 256) * 8);   // also the 256 partial sums of dL/dlam
+  L.dbar = take(std::max<size_t>(nf, 256) * 8);   // also the 256 partial sums of dL/dlam and of the squared error
   L.red = take(nf * 8 + 64);
   L.tiles = take((size_t)p->n_slots * 256 * 8);
   L.tinv = take((size_t)p->n_rt * 256 * 8);

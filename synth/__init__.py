@@ -318,3 +318,19 @@ def cycle_observations(p: Problem, cycles: int, shift: int = 1, config: int = 4)
         Y = observe(x, p.obs_idx, p.r_diag, p.N, rng(config, STREAM_OBS_NOISE, t), rng(config, STREAM_PERTURB, t))
         out.append((x, Y))
     return out
+
+
+def cycle_truth_and_obs(p: Problem, cycles: int, shift: int = 1, config: int = 4) -> List[tuple]:
+    """Truth x_t and unperturbed observations y_t = x_t[obs] + e_t, e_t ~ N(0, R),
+    of `cycles` assimilation times: x_t is the synthetic forecast applied t
+    times to p.x_true.  The perturbation of y_t into Y^s is left to the method."""
+    out = []
+    x = np.asarray(p.x_true, np.float64)
+    sd = np.sqrt(p.r_diag)
+    for t in range(cycles):
+        if t > 0:
+            x = linear_forecast(x, p.geometry, shift)
+        y = x[p.obs_idx] + sd * rng(config, STREAM_OBS_NOISE, 1000 + t).standard_normal(p.obs_idx.shape[0])
+        out.append((x, y))
+    return out
+

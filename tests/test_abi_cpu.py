@@ -95,3 +95,19 @@ def test_plan_rejects_bad_input(case):
     with pytest.raises(EnkfmcError) as e:
         Plan(geo, N, obs)
     assert e.value.code == "EINVAL"
+
+
+def test_cycle_entry_points_validate_on_the_host():
+    """NULL arguments are EINVAL and a plan without workspace is ESTATE, before
+    any device work (the fake pointers below are never dereferenced)."""
+    import ctypes
+    geo = synth.geometry(12, 8, [2], True, 3, 2, 1, 1)
+    plan = Plan(geo, 10, np.array([1, 5, 9], np.int32))
+    lib = plan.lib
+    fake = ctypes.c_void_p(256)
+    assert lib.enkfmc_perturb_observations(plan._h, None, fake, 1, 0, fake, None) == -1
+    assert lib.enkfmc_perturb_observations(plan._h, fake, fake, 1, 0, fake, None) == -7
+    assert lib.enkfmc_analysis_sq_error(plan._h, fake, 1, 10, None, fake, None) == -1
+    assert lib.enkfmc_analysis_sq_error(plan._h, fake, 7, 10, fake, fake, None) == -1
+    assert lib.enkfmc_analysis_sq_error(plan._h, fake, 1, 9, fake, fake, None) == -1
+    assert lib.enkfmc_analysis_sq_error(plan._h, fake, 1, 10, fake, fake, None) == -7
