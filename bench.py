@@ -65,6 +65,54 @@ def traffic_per_launch():
     return TRAFFIC["bytes_per_launch"]
 
 
+def study(cycles: int) -> None:
+    """RMSE of eq. (18) and time per assimilation cycle at the T-63 size against
+    the ridge (at 24x12 sub-domains) and against the number of sub-domains Delta
+    (at ridge 0.1), the synthetic analogue of the paper's Section 4.3.  Prints
+    one JSON line."""
+    import torch
+
+    import synth
+    from paper_1606_00807_amd import Plan
+    from paper_1606_00807_amd.cycling import assimilate
+
+    prob = synth.make_t63()
+    obs = synth.cycle_truth_and_obs(prob, cycles)
+    ys = [torch.as_tensor(y).cuda() for _, y in obs]
+    refs = [torch.as_tensor(x).cuda() for x, _ in obs]
+    r = torch.as_tensor(prob.r_diag).cuda()
+    Xb = torch.as_tensor(prob.Xb).cuda()
+    nl = int(sum(prob.geometry["nlev"]))
+    gy, gx = prob.geometry["ny"], prob.geometry["nx"]
+    e_b = float(torch.sum((Xb.double().mean(1) - refs[0]) ** 2))
+
+    def forecast(X):
+        return torch.roll(X.reshape(nl, gy, gx, -1), 1, dims=2).reshape(X.shape).contiguous()
+
+    rows = []
+    for sdx, sdy, lam in [(24, 12, 1e-3), (24, 12, 1e-2), (24, 12, 1e-1), (24, 12, 1.0),
+                          (6, 3, 0.1), (12, 6, 0.1), (48, 24, 0.1)]:
+        geo = dict(prob.geometry)
+        geo["sdx"], geo["sdy"] = sdx, sdy
+        plan = Plan(geo, prob.N, prob.obs_idx)
+        assimilate(plan, Xb, ys[:1], r, lam, forecast, seed=1606, x_ref=refs[:1])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = assimilate(plan, Xb, ys, r, lam, forecast, seed=1606, x_ref=refs)
+        torch.cuda.synchronize()
+        tc = (time.perf_counter() - t) / cycles
+        row = {"sdx": sdx, "sdy": sdy, "ridge": lam, "n_fit": plan.info["n_fit"], "ms_per_cycle": tc * 1e3,
+               "rmse_eq18": res.rmse, "sq_err": res.sq_err.cpu().tolist()}
+        rows.append(row)
+        log(f"study: Delta={sdx}x{sdy} ridge={lam:g}: {tc * 1e3:.1f} ms/cycle, RMSE {res.rmse:.2f}, "
+            f"squared errors {[round(v) for v in row['sq_err']]}")
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+    print(json.dumps({"study": "t63 cycles vs ridge and sub-domain count", "cycles": cycles,
+                      "background_sq_err": e_b, "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +127,8 @@ def main():
                     help="also time fit + analyze + enkfmc_analyze_backward this many times (0: skip)")
     ap.add_argument("--cycles", type=int, default=4,
                     help="also time this many assimilation cycles (Alg. 1) with the zonal-shift forecast (0: skip)")
+    ap.add_argument("--study", action="store_true",
+                    help="only run the ridge / sub-domain-count study of the assimilation cycles")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (HBM counter calibration)")
     args = ap.parse_args()
@@ -95,6 +145,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.study:
+        study(max(args.cycles, 1))
+        return
     t0 = time.time()
     prob = synth.make_t63()
     log(f"generated T-63 workload n={prob.n} N={prob.N} m={prob.m} in {time.time() - t0:.1f}s")

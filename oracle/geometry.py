@@ -87,6 +87,8 @@ def validate(geo: Dict) -> None:
 def box(geo: Dict, k: int) -> Box:
     """Extended box of sub-domain k = ky * sdx + kx (R4, R12)."""
     nx, ny, sdx, r = geo["nx"], geo["ny"], geo["sdx"], geo["r_h"]
+    if not 0 <= k < sdx * geo["sdy"]:
+        raise OracleError("EINVAL", f"sub-domain {k} outside 0..{sdx * geo['sdy'] - 1}")
     kx, ky = k % sdx, k // sdx
     x0, x1 = tile_bounds(nx, sdx, kx)
     y0, y1 = tile_bounds(ny, geo["sdy"], ky)

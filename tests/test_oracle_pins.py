@@ -280,3 +280,10 @@ def test_adjoint_dot_product_of_local_solve():
     v, w = g.standard_normal(fac.pat.n_sd), g.standard_normal(fac.pat.n_sd)
     cf = sla.cho_factor(Amat)
     assert abs(sla.cho_solve(cf, v) @ w - v @ sla.cho_solve(cf, w)) < 1e-10 * np.linalg.cond(Amat) * 1e-3 + 1e-9
+
+
+def test_subdomain_index_out_of_range_is_an_error():
+    geo = synth.geometry(12, 8, [2], True, 3, 2, 1, 1)
+    for k in (-1, 6, 100):
+        with pytest.raises(OracleError):
+            G.box(geo, k)
