@@ -18,6 +18,8 @@
 //
 // v_mfma_f64_16x16x4 conventions (lane l = 16q + c): A operand A[c][q],
 // B operand B[q][c], accumulator register r holds element (4r + q, c).
+#include <algorithm>
+
 #include "device.h"
 
 namespace enkfmc {
@@ -26,6 +28,14 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
 __device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// Orders this wavefront's LDS accesses: LDS executes one wavefront's
+// operations in issue order, so this only keeps the compiler from moving
+// memory operations across it.
+__device__ inline void wave_lds_sync() {
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
 
 // Dense tiles T_RC (row-major) of row tile R, and the inverse of T_RR.
 // One wavefront per (block, row tile).  Each lane fills whole tile rows: for
@@ -348,6 +358,122 @@ __global__ __launch_bounds__(64) void k_fwd_sweep(const Block *__restrict__ bloc
   }
 }
 
+// The same sweep with this wavefront's last W row tiles of Z kept in LDS, a
+// ring of 16x16 tiles (row-major) where row tile R sits at slot R mod W.  Every
+// stored T_RC has R - C <= W (W is the plan's largest such distance), so each
+// product T_RC Z_C reads Z_C from the ring rather than from memory.  The T
+// tiles of a row tile are taken in batches of up to kSweepBatch, and the next
+// batch (of this row tile or the next) loads while the current one is summed;
+// G and the inverse diagonal tile of the next row tile load one row tile
+// ahead.  The four k-steps of a tile go to two accumulators, halving the
+// dependent MFMA chain.  The grid is one-dimensional over (block, member
+// tile), numbered so that the member tiles of a block run on one XCD and share
+// its T tiles in L2.
+constexpr int kSweepBatch = 16;
+
+__global__ __launch_bounds__(64) void k_fwd_sweep_ring(const Block *__restrict__ blocks, int ng,
+                                                       const int64_t *__restrict__ rt_ptr,
+                                                       const int32_t *__restrict__ rt_col,
+                                                       const int32_t *__restrict__ rt_slot,
+                                                       const double *__restrict__ tiles,
+                                                       const double *__restrict__ tinv, int N, int W,
+                                                       double *__restrict__ Z) {
+  extern __shared__ double ring[];
+  const int64_t lg = xcd_contiguous(blockIdx.x, gridDim.x);
+  const Block B = blocks[lg / ng];
+  const int cc = (int)(lg % ng);
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int colj = 16 * cc + c;
+  const bool colok = colj < N;
+  double *Zb = Z + B.row0 * N;
+  if (B.nrt <= 0) return;
+  const int64_t *rp = rt_ptr + B.rt0;
+  auto load_g = [&](int R, d4 &g, double(&ti)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * R + 4 * r + q;
+      g[r] = (row < B.n && colok) ? Zb[(int64_t)row * N + colj] : 0.0;
+    }
+    const double *Ti = tinv + (B.rt0 + R) * 256 + c * 16 + q;
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) ti[kc] = Ti[4 * kc];
+  };
+  // batch cursor: row tile Rl, next tile tl of its list
+  int Rl = 0;
+  int64_t tl = rp[0];
+  auto load_batch = [&](double(&tv)[kSweepBatch][4], int(&cs)[kSweepBatch], int &cnt, int &R, bool &last) {
+    const int64_t end = rp[Rl + 1];
+    cnt = (int)(end - tl < kSweepBatch ? end - tl : kSweepBatch);
+    R = Rl;
+#pragma unroll
+    for (int j = 0; j < kSweepBatch; ++j) {
+      if (j < cnt) {
+        const double *Tt = tiles + (int64_t)rt_slot[tl + j] * 256 + c * 16 + q;
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) tv[j][kc] = Tt[4 * kc];
+        cs[j] = rt_col[tl + j];
+      }
+    }
+    tl += cnt;
+    last = tl == end;
+    if (last) ++Rl;
+  };
+  double ta[kSweepBatch][4], tb[kSweepBatch][4];
+  int ca[kSweepBatch], cb[kSweepBatch];
+  int na = 0, nb = 0, Ra = 0, Rb = 0;
+  bool la = true, lb = true;
+  load_batch(ta, ca, na, Ra, la);
+  d4 acc0, acc1 = d4{0.0, 0.0, 0.0, 0.0}, gn = d4{0.0, 0.0, 0.0, 0.0};
+  double ti[4], tin[4] = {0.0, 0.0, 0.0, 0.0};
+  load_g(0, acc0, ti);
+  if (B.nrt > 1) load_g(1, gn, tin);
+  while (true) {
+    const bool more = Rl < B.nrt;
+    if (more) load_batch(tb, cb, nb, Rb, lb);
+#pragma unroll
+    for (int j = 0; j < kSweepBatch; ++j) {
+      if (j < na) {
+        const double *zr = ring + (ca[j] % W) * 256 + 16 * q + c;   // B operand: Z_C(4kc + q, c)
+        acc0 = mfma64(-ta[j][0], zr[0], acc0);
+        acc1 = mfma64(-ta[j][2], zr[128], acc1);
+        acc0 = mfma64(-ta[j][1], zr[64], acc0);
+        acc1 = mfma64(-ta[j][3], zr[192], acc1);
+      }
+    }
+    if (la) {
+      // row tile Ra is complete: Z_Ra = T_RaRa^-1 (G_Ra - sum_C T_RaC Z_C)
+      const d4 acc = acc0 + acc1;
+      d4 out = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) out = mfma64(ti[kc], acc[kc], out);
+      double *slot = ring + (Ra % W) * 256 + 16 * q + c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        slot[64 * r] = out[r];
+        const int row = 16 * Ra + 4 * r + q;
+        if (colok && row < B.n) Zb[(int64_t)row * N + colj] = out[r];
+      }
+      wave_lds_sync();
+      if (Ra + 1 >= B.nrt) break;
+      acc0 = gn;
+      acc1 = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) ti[kc] = tin[kc];
+      if (Ra + 2 < B.nrt) load_g(Ra + 2, gn, tin);
+    }
+    // every row tile ends a batch, so a batch remains while row tiles do
+#pragma unroll
+    for (int j = 0; j < kSweepBatch; ++j) {
+      ca[j] = cb[j];
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) ta[j][kc] = tb[j][kc];
+    }
+    na = nb;
+    Ra = Rb;
+    la = lb;
+  }
+}
+
 // X_a = X_b + Z on interior rows (each component has exactly one source row).
 template <typename TX, typename TO>
 __global__ __launch_bounds__(256) void k_mapback(const TX *__restrict__ Xb, int64_t ld,
@@ -359,6 +485,10 @@ __global__ __launch_bounds__(256) void k_mapback(const TX *__restrict__ Xb, int6
   const int c = (int)(idx % N);
   Xa[idx] = (TO)((double)Xb[g * ld + c] + Z[(int64_t)src[g] * N + c]);
 }
+
+// Largest ring of Z tiles a sweep keeps in LDS (one workgroup's dynamic LDS);
+// plans that need more use the sweep without a ring.
+constexpr size_t kRingMaxBytes = 64 * 1024;
 
 int max_block_tiles(const enkfmc_plan *p) {
   int mx = 0;
@@ -383,8 +513,14 @@ hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const
                      d.dvec, V, p->N, out);
   phase_end(p, ENKFMC_PH_DUAL_G, s);
   phase_begin(p, ENKFMC_PH_SWEEP, s);
-  hipLaunchKernelGGL(k_fwd_sweep, dim3(nb, (p->N + 15) / 16), dim3(64), 0, s, d.blocks, d.rt_ptr, d.rt_col, d.rt_slot,
-                     d.tiles, d.tinv, p->N, out);
+  const int ng = (p->N + 15) / 16;
+  const int W = std::max(1, (int)p->max_rt_back);
+  if ((size_t)W * 2048 <= kRingMaxBytes)
+    hipLaunchKernelGGL(k_fwd_sweep_ring, dim3(nb * (unsigned)ng), dim3(64), (size_t)W * 2048, s, d.blocks, ng,
+                       d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tinv, p->N, W, out);
+  else
+    hipLaunchKernelGGL(k_fwd_sweep, dim3(nb, (unsigned)ng), dim3(64), 0, s, d.blocks, d.rt_ptr, d.rt_col, d.rt_slot,
+                       d.tiles, d.tinv, p->N, out);
   phase_end(p, ENKFMC_PH_SWEEP, s);
   return hipGetLastError();
 }

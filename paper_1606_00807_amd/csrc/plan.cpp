@@ -233,7 +233,7 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
   // block-sparse tiling of each block's T (16-row tiles)
   p->rt_ptr.assign(1, 0);
   p->rt_col.clear(); p->rt_slot.clear();
-  p->n_rt = 0; p->n_slots = 0; p->max_rt_tiles = 0;
+  p->n_rt = 0; p->n_slots = 0; p->max_rt_tiles = 0; p->max_rt_back = 0;
   for (Block &B : p->blocks) {
     B.rt0 = p->n_rt;
     for (int32_t R = 0; R < B.nrt; ++R) {
@@ -247,6 +247,7 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
       for (int32_t c : cs) { p->rt_col.push_back(c); p->rt_slot.push_back((int32_t)p->n_slots++); }
       p->rt_ptr.push_back((int64_t)p->rt_col.size());
       p->max_rt_tiles = std::max(p->max_rt_tiles, (int32_t)cs.size());
+      if (!cs.empty()) p->max_rt_back = std::max(p->max_rt_back, R - cs.front());
       ++p->n_rt;
     }
   }

@@ -84,6 +84,7 @@ struct enkfmc_plan {
   std::vector<uint16_t> tile_eoff;
   int64_t n_rt = 0, n_slots = 0;
   int32_t max_rt_tiles = 0;
+  int32_t max_rt_back = 0;     // largest R - C over the stored tiles T_RC (C < R) of any block
   int64_t n_fit = 0, nnz = 0, m_local = 0, sum_F = 0, sum_S = 0, sum_Q = 0;
   int32_t max_p = 0, max_bn = 0, max_bm = 0;
   enkfmc::Layout lay{};
