@@ -168,6 +168,112 @@ __global__ __launch_bounds__(64) void k_bwd_sweep(const Block *__restrict__ bloc
   }
 }
 
+// The same backward sweep with this wavefront's F tiles of the last W column
+// tiles done (rows C+1 .. C+W) in an LDS ring, slot R mod W, so T_RC^T F_R reads
+// F_R from LDS (every stored T_RC has R - C <= W).  The T tiles of column tile
+// C (its list trimmed to rows <= Cs) load as one batch of up to kSweepBatch
+// while the previous column tile's batch is summed.  Grid: one-dimensional
+// over (block, observation tile), member tiles of a block adjacent (one XCD).
+constexpr int kBwdBatch = 16;
+
+__global__ __launch_bounds__(64) void k_bwd_sweep_ring(const Block *__restrict__ blocks, int og,
+                                                       const int64_t *__restrict__ ct_ptr,
+                                                       const int32_t *__restrict__ ct_row,
+                                                       const int32_t *__restrict__ ct_slot,
+                                                       const int32_t *__restrict__ bobs_row,
+                                                       const int32_t *__restrict__ ot_jmax,
+                                                       const double *__restrict__ tiles,
+                                                       const double *__restrict__ tinv, int W,
+                                                       double *__restrict__ F) {
+  extern __shared__ double ring[];
+  const int64_t lg = xcd_contiguous(blockIdx.x, gridDim.x);
+  const Block B = blocks[lg / og];
+  const int oc = (int)(lg % og);
+  if (16 * oc >= B.m) return;
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int o = 16 * oc + c;
+  const int jo = o < B.m ? bobs_row[B.obs0 + o] : -1;
+  const int ldf = B.ldf;
+  double *Fb = F + B.F0;
+  const int Cs = ot_jmax[B.ot0 + oc] >> 4;
+  for (int C = B.nrt - 1; C > Cs; --C) {
+    double *Fc = Fb + (int64_t)(16 * C) * ldf + 16 * oc + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Fc[(int64_t)(4 * r + q) * ldf] = 0.0;
+  }
+  const int64_t *cp = ct_ptr + B.rt0;
+  // batch cursor: column tile Cl (descending), its list trimmed to rows <= Cs
+  int Cl = Cs;
+  auto load_batch = [&](double(&tv)[kBwdBatch][4], int(&rs)[kBwdBatch], int &cnt) {
+    const int64_t s0 = cp[Cl];
+    int64_t s1 = cp[Cl + 1];
+    while (s1 > s0 && ct_row[s1 - 1] > Cs) --s1;
+    cnt = (int)(s1 - s0 < kBwdBatch ? s1 - s0 : kBwdBatch);
+#pragma unroll
+    for (int j = 0; j < kBwdBatch; ++j) {
+      if (j < cnt) {
+        const double *Tt = tiles + (int64_t)ct_slot[s0 + j] * 256 + q * 16 + c;   // A operand: T_RC(4kc + q, c)
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) tv[j][kc] = Tt[64 * kc];
+        rs[j] = ct_row[s0 + j];
+      }
+    }
+    --Cl;
+    return s1 - s0;
+  };
+  double ta[kBwdBatch][4], tb[kBwdBatch][4];
+  int ra[kBwdBatch], rb[kBwdBatch];
+  int na = 0, nb = 0;
+  int64_t fulla = load_batch(ta, ra, na), fullb = 0;
+  for (int C = Cs; C >= 0; --C) {
+    if (C > 0) fullb = load_batch(tb, rb, nb);
+    const double *Ti = tinv + (B.rt0 + C) * 256 + q * 16 + c;
+    double ti[4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) ti[kc] = Ti[64 * kc];
+    d4 acc0, acc1 = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc0[r] = (16 * C + 4 * r + q == jo) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < kBwdBatch; ++j) {
+      if (j < na) {
+        const double *fr = ring + (ra[j] % W) * 256 + 16 * q + c;   // B operand: F_R(4kc + q, o)
+        acc0 = mfma64(-ta[j][0], fr[0], acc0);
+        acc1 = mfma64(-ta[j][2], fr[128], acc1);
+        acc0 = mfma64(-ta[j][1], fr[64], acc0);
+        acc1 = mfma64(-ta[j][3], fr[192], acc1);
+      }
+    }
+    // entries beyond the first batch of a long list: T from memory, F_R from the ring
+    for (int64_t t = cp[C] + kBwdBatch; t < cp[C] + fulla; ++t) {
+      const double *Tt = tiles + (int64_t)ct_slot[t] * 256 + q * 16 + c;
+      const double *fr = ring + (ct_row[t] % W) * 256 + 16 * q + c;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) acc0 = mfma64(-Tt[64 * kc], fr[64 * kc], acc0);
+    }
+    const d4 acc = acc0 + acc1;
+    d4 out = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) out = mfma64(ti[kc], acc[kc], out);
+    double *slot = ring + (C % W) * 256 + 16 * q + c;
+    double *Fc = Fb + (int64_t)(16 * C) * ldf + 16 * oc + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      slot[64 * r] = out[r];
+      Fc[(int64_t)(4 * r + q) * ldf] = out[r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < kBwdBatch; ++j) {
+      ra[j] = rb[j];
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) ta[j][kc] = tb[j][kc];
+    }
+    na = nb;
+    fulla = fullb;
+  }
+}
+
 // S = R + F^T D F (lower tiles, stride ldf); one wavefront per (block, tile
 // column J, chunk of up to 8 tile rows I >= J).
 __global__ __launch_bounds__(64) void k_dual_S(const Block *__restrict__ blocks, const int32_t *__restrict__ bobs_o,
@@ -533,8 +639,13 @@ static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   const unsigned oc = (unsigned)((p->max_bm + 15) / 16);
   if (p->max_bm > 0) {
     phase_begin(p, ENKFMC_PH_DUAL_F, s);
-    hipLaunchKernelGGL(k_bwd_sweep, dim3(nb, oc), dim3(64), 0, s, d.blocks, d.ct_ptr, d.ct_row, d.ct_slot, d.bobs_row,
-                       d.ot_jmax, d.tiles, d.tinv, d.F);
+    const int W = std::max(1, (int)p->max_rt_back);
+    if ((size_t)W * 2048 <= kRingMaxBytes)
+      hipLaunchKernelGGL(k_bwd_sweep_ring, dim3(nb * oc), dim3(64), (size_t)W * 2048, s, d.blocks, (int)oc, d.ct_ptr,
+                         d.ct_row, d.ct_slot, d.bobs_row, d.ot_jmax, d.tiles, d.tinv, W, d.F);
+    else
+      hipLaunchKernelGGL(k_bwd_sweep, dim3(nb, oc), dim3(64), 0, s, d.blocks, d.ct_ptr, d.ct_row, d.ct_slot,
+                         d.bobs_row, d.ot_jmax, d.tiles, d.tinv, d.F);
     phase_end(p, ENKFMC_PH_DUAL_F, s);
     phase_begin(p, ENKFMC_PH_DUAL_S, s);
     hipLaunchKernelGGL(k_dual_S, dim3(nb, oc, (oc + 7) / 8), dim3(64), 0, s, d.blocks, d.bobs_o, d.ot_jmax, d.F,
