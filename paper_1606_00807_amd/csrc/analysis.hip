@@ -38,21 +38,27 @@ __device__ inline void wave_lds_sync() {
 }
 
 // Dense tiles T_RC (row-major) of row tile R, and the inverse of T_RR.
-// One wavefront per (block, row tile).  Each lane fills whole tile rows: for
-// (row i, column tile C) the row's entries in [16C, 16C + 16) start at the
-// planned offset and end where the next tile's begin; they are scattered into
-// a zeroed row of the lane's LDS and written out as 16 values.  The diagonal
-// tile also goes to LDS, where 16 lanes invert it.
+// One wavefront per (block, row tile).  The CSR entries of the tile's 16 rows
+// are contiguous; the wavefront reads them in coalesced runs of 64 and
+// scatters each into its tile, assembled in LDS (zeros elsewhere) up to
+// kTileChunk tiles at a time, then writes the tiles out whole.  An entry's row
+// is found among the 17 row starts (uniform registers), its tile's place in
+// the row tile's list through a small LDS map indexed by R - C.  The diagonal
+// tile stays in LDS, where 16 lanes invert it.
+constexpr int kTileChunk = 13;
+constexpr int kTileMap = 128;
+constexpr int kBuildUnroll = 8;
+
 __global__ __launch_bounds__(64) void k_build_tiles(const Block *__restrict__ blocks,
                                                     const int64_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ col, const double *__restrict__ tval,
                                                     const int64_t *__restrict__ rt_ptr,
                                                     const int32_t *__restrict__ rt_col,
-                                                    const int32_t *__restrict__ rt_slot,
-                                                    const uint16_t *__restrict__ teoff, double *__restrict__ tiles,
+                                                    const int32_t *__restrict__ rt_slot, double *__restrict__ tiles,
                                                     double *__restrict__ tinv, double *__restrict__ tdiag) {
+  __shared__ double tb[kTileChunk * 256];
   __shared__ double diag[256];
-  __shared__ double srow[64 * 17];
+  __shared__ int32_t tmap[kTileMap];
   const Block B = blocks[blockIdx.x];
   const int R = blockIdx.y;
   if (R >= B.nrt) return;
@@ -60,31 +66,69 @@ __global__ __launch_bounds__(64) void k_build_tiles(const Block *__restrict__ bl
   const int64_t rt = B.rt0 + R;
   const int64_t t0 = rt_ptr[rt];
   const int nt = (int)(rt_ptr[rt + 1] - t0);
-  for (int pr = lane; pr < 16 * (nt + 1); pr += 64) {
-    const int i = pr & 15, t = pr >> 4;          // t == nt: the diagonal tile
-    const int C = t < nt ? rt_col[t0 + t] : R;
-    const int row = 16 * R + i;
-    double *sr = srow + lane * 17;
+  const int nrow = B.n - 16 * R < 16 ? B.n - 16 * R : 16;
+  // row starts 0..nrow (the entries of row i are [rs_i, rs_{i+1}))
+  const int64_t myrs = lane <= nrow ? row_ptr[B.row0 + 16 * R + lane] : 0;
+  int64_t rs[17];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) sr[j] = 0.0;
-    if (row < B.n) {
-      const int64_t ka = row_ptr[B.row0 + row];
-      const int64_t e0 = ka + teoff[16 * (t0 + rt + t) + i];
-      const int64_t e1 = t < nt ? ka + teoff[16 * (t0 + rt + t + 1) + i] : row_ptr[B.row0 + row + 1];
+  for (int i = 0; i <= 16; ++i) {
+    const long long v = __shfl((long long)myrs, i <= nrow ? i : nrow, 64);
+    rs[i] = (int64_t)v;
+  }
+  const int64_t k0 = rs[0], k1 = rs[16];
+  for (int t = lane; t < nt; t += 64) {
+    const int d = R - rt_col[t0 + t];
+    if (d < kTileMap) tmap[d] = t;
+  }
+  for (int tlo = 0; tlo == 0 || tlo < nt; tlo += kTileChunk) {
+    const int thi = nt - tlo < kTileChunk ? nt : tlo + kTileChunk;
+    for (int e = lane; e < (thi - tlo) * 256; e += 64) tb[e] = 0.0;
+    if (tlo == 0)
+      for (int e = lane; e < 256; e += 64) diag[e] = 0.0;
+    wave_lds_sync();
+    // kBuildUnroll runs of 64 entries are loaded before any is scattered
+    for (int64_t kb = k0; kb < k1; kb += 64 * kBuildUnroll) {
+      int cs[kBuildUnroll];
+      double vs[kBuildUnroll];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t k = e0 + e;
-        if (k < e1) sr[col[k] - 16 * C] = tval[k];
+      for (int u = 0; u < kBuildUnroll; ++u) {
+        const int64_t k = kb + 64 * u + lane;
+        cs[u] = k < k1 ? col[k] : 0;
+        vs[u] = k < k1 ? tval[k] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kBuildUnroll; ++u) {
+        const int64_t k = kb + 64 * u + lane;
+        if (k >= k1) continue;
+        int i = 0;
+#pragma unroll
+        for (int h = 1; h < 16; ++h) i += k >= rs[h] ? 1 : 0;
+        const int C = cs[u] >> 4, j = cs[u] & 15;
+        if (C == R) {
+          if (tlo == 0) diag[i * 16 + j] = vs[u];
+        } else {
+          int t;
+          if (R - C < kTileMap) {
+            t = tmap[R - C];
+          } else {   // list position by bisection (rt_col ascending)
+            int lo = 0, hi = nt - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (rt_col[t0 + mid] < C) lo = mid + 1; else hi = mid;
+            }
+            t = lo;
+          }
+          if (t >= tlo && t < thi) tb[(t - tlo) * 256 + i * 16 + j] = vs[u];
+        }
       }
     }
-    double v[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = sr[j];
-    double *dst = (t < nt ? tiles + (int64_t)rt_slot[t0 + t] * 256 : diag) + i * 16;
-#pragma unroll
-    for (int j = 0; j < 16; j += 2) *(d2 *)(dst + j) = d2{v[j], v[j + 1]};
+    wave_lds_sync();
+    for (int e = lane; e < (thi - tlo) * 128; e += 64) {
+      const int tt = e >> 7, w = 2 * (e & 127);
+      *(d2 *)(tiles + (int64_t)rt_slot[t0 + tlo + tt] * 256 + w) = d2{tb[tt * 256 + w], tb[tt * 256 + w + 1]};
+    }
+    wave_lds_sync();
   }
-  __syncthreads();
   for (int e = lane; e < 256; e += 64) tdiag[rt * 256 + e] = diag[e];   // strictly lower T_RR
   if (lane < 16) {
     // column `lane` of (I + L)^-1 by forward substitution
@@ -605,8 +649,7 @@ int max_block_tiles(const enkfmc_plan *p) {
 hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s) {
   phase_begin(p, ENKFMC_PH_TILES, s);
   hipLaunchKernelGGL(k_build_tiles, dim3((unsigned)p->blocks.size(), (unsigned)max_block_tiles(p)), dim3(64), 0, s,
-                     d.blocks, d.row_ptr, d.col, d.tval, d.rt_ptr, d.rt_col, d.rt_slot, d.tile_eoff, d.tiles, d.tinv,
-                     d.tdiag);
+                     d.blocks, d.row_ptr, d.col, d.tval, d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tinv, d.tdiag);
   phase_end(p, ENKFMC_PH_TILES, s);
   return hipGetLastError();
 }
