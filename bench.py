@@ -49,9 +49,9 @@ def fit_flops(counts, N):
 # counters, each scaled by what the same counter reads for a plain copy of
 # known size.  Valid only for the kernel source it was taken on: a changed
 # source reports null.
-TRAFFIC = {"fit_batched_sha256": "44916179aa3efd7e8fd50a8c195b4d1e901ce3fbde80ea710df8b236245eb221",
-           "fetch_bytes": 1.2694e10, "write_bytes": 2.0294e9, "bytes_per_launch": 1.4724e10,
-           "fetch_scale": 1.9998, "write_scale": 1.0}
+TRAFFIC = {"fit_batched_sha256": "242368314988117ff96889bbb9ce5cc1a9c941b8723d5ad75a2bd48ff1774bfe",
+           "fetch_bytes": 1.7616e+09, "write_bytes": 9.6520e+08, "bytes_per_launch": 2.7268e+09,
+           "fetch_scale": 1.9999, "write_scale": 1.0}
 
 
 def traffic_per_launch():
