@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-subdomains", type=int, default=6)
+    ap.add_argument("--cpu-subdomains", type=int, default=14)
     ap.add_argument("--adjoint-steps", type=int, default=3,
                     help="also time fit + analyze + enkfmc_analyze_backward this many times (0: skip)")
     ap.add_argument("--cycles", type=int, default=4,
