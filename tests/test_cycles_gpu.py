@@ -11,7 +11,7 @@ The GPU chain runs through the torch.autograd wrapper, which recomputes each
 cycle's fit and analysis in the reverse pass.  It is compared with the oracle's
 analytic gradient (the same chain rule over the oracle's per-cycle adjoint) to
 1e-5, and with Richardson-extrapolated central differences of the GPU forward
-chain.
+chain along eight random directions for X_b and for log r, and the ridge.
 """
 import sys
 
@@ -109,7 +109,7 @@ def test_chain_gradient_matches_finite_differences(chain):
 
     X0, r0, l0 = Xb0.detach(), logr.detach(), lam.detach()
     with torch.no_grad():
-        for _ in range(2):
+        for _ in range(8):   # eight random directions per parameter group
             V = torch.as_tensor(g.standard_normal(p.Xb.shape)).cuda()
             fd = richardson(lambda e: float(loss(X0 + e * V, r0, l0)), 1e-4)
             ad = float(torch.sum(Xb0.grad * V))

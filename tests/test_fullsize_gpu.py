@@ -9,8 +9,8 @@ The oracle cannot redo the whole state quickly, so it recomputes samples:
     lies in the extended boxes of exactly four sub-domains, so the oracle's
     adjoint restricted to those four gives dX_b and dlog r there exactly;
 and directional finite differences of L = <Gbar, X_a> (Richardson-extrapolated
-central differences) check the GPU adjoint against the GPU forward pass over
-the whole state.
+central differences, eight random directions for X_b and for log r, and the
+ridge) check the GPU adjoint against the GPU forward pass over the whole state.
 """
 import sys
 
@@ -136,16 +136,17 @@ def test_t63_adjoint_directional_finite_differences(t63):
         d2 = (f(h / 2) - f(-h / 2)) / h
         return (4 * d2 - d1) / 3
 
-    V = torch.as_tensor(g.standard_normal((p.n, p.N))).cuda()
-    fd = richardson(lambda e: L(X + e * V, r0, p.ridge), 1e-4)
-    ad = float(torch.sum(dXb * V))
-    _say(f"[t63 fd] X_b: fd={fd:.10e} adjoint={ad:.10e}")
-    assert abs(fd - ad) <= 1e-6 * abs(fd)
-    v = torch.as_tensor(g.standard_normal(p.m)).cuda()
-    fd = richardson(lambda e: L(X, r0 * torch.exp(e * v), p.ridge), 1e-4)
-    ad = float(torch.sum(dlogR * v))
-    _say(f"[t63 fd] log r: fd={fd:.10e} adjoint={ad:.10e}")
-    assert abs(fd - ad) <= 1e-6 * abs(fd)
+    for d in range(8):   # eight random directions per parameter group
+        V = torch.as_tensor(g.standard_normal((p.n, p.N))).cuda()
+        fd = richardson(lambda e: L(X + e * V, r0, p.ridge), 1e-4)
+        ad = float(torch.sum(dXb * V))
+        _say(f"[t63 fd {d}] X_b: fd={fd:.10e} adjoint={ad:.10e}")
+        assert abs(fd - ad) <= 1e-6 * abs(fd)
+        v = torch.as_tensor(g.standard_normal(p.m)).cuda()
+        fd = richardson(lambda e: L(X, r0 * torch.exp(e * v), p.ridge), 1e-4)
+        ad = float(torch.sum(dlogR * v))
+        _say(f"[t63 fd {d}] log r: fd={fd:.10e} adjoint={ad:.10e}")
+        assert abs(fd - ad) <= 1e-6 * abs(fd)
     fd = richardson(lambda e: L(X, r0, p.ridge + e), 1e-6)
     _say(f"[t63 fd] lam: fd={fd:.10e} adjoint={float(dlam):.10e}")
     assert abs(fd - float(dlam)) <= 1e-6 * abs(fd)
