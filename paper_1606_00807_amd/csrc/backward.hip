@@ -170,11 +170,12 @@ __global__ __launch_bounds__(64) void k_adj_factor_tiles(const Block *__restrict
                                                          const double *__restrict__ tiles,
                                                          const double *__restrict__ tdiag,
                                                          const double *__restrict__ dvec, const double *__restrict__ Z,
-                                                         const double *__restrict__ W, int N,
+                                                         const double *__restrict__ W, int N, int ntile,
                                                          double *__restrict__ dbar, double *__restrict__ bbar) {
   extern __shared__ double sm[];
-  const Block B = blocks[blockIdx.x];
-  const int R = blockIdx.y;
+  int bi, R;
+  block_tile(ntile, bi, R);
+  const Block B = blocks[bi];
   if (R >= B.nrt) return;
   const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
   const int ldn = N + 1;
@@ -466,11 +467,12 @@ __global__ __launch_bounds__(64) void k_adj_ubar_tiles(const Block *__restrict__
                                                        const double *__restrict__ tiles,
                                                        const double *__restrict__ tdiag, const double *__restrict__ sv,
                                                        const double *__restrict__ e1, const double *__restrict__ e2,
-                                                       int N, double *__restrict__ ubar) {
+                                                       int N, int ntile, double *__restrict__ ubar) {
   constexpr int kMaxCT = 8;                    // member tiles (N <= 128)
   __shared__ double sS[16 * 17];
-  const Block B = blocks[blockIdx.x];
-  const int C = blockIdx.y;
+  int bi, C;
+  block_tile(ntile, bi, C);
+  const Block B = blocks[bi];
   if (C >= B.nrt) return;
   const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
   const int nct = (N + 15) >> 4;
@@ -651,9 +653,10 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
     const size_t lds = (size_t)(32 * (N + 1) + 16 * 17) * 8;
     e = hipFuncSetAttribute((const void *)k_adj_factor_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_factor_tiles, dim3(nb, (unsigned)max_block_tiles(p)), dim3(64), lds, s, d.blocks,
-                       d.row_ptr, d.col, d.rt_ptr, d.rt_col, d.rt_slot, d.tile_eoff, d.tiles, d.tdiag, d.dvec, d.Z, d.W,
-                       N, d.dbar, d.aux3);
+    const int mt = max_block_tiles(p);
+    hipLaunchKernelGGL(k_adj_factor_tiles, dim3(nb * (unsigned)mt), dim3(64), lds, s, d.blocks, d.row_ptr, d.col,
+                       d.rt_ptr, d.rt_col, d.rt_slot, d.tile_eoff, d.tiles, d.tdiag, d.dvec, d.Z, d.W, N, mt, d.dbar,
+                       d.aux3);
   }
   phase_end(p, ENKFMC_PH_ADJ_FACTOR, s);
   phase_begin(p, ENKFMC_PH_ADJ_REGRESS, s);
@@ -668,9 +671,10 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   }
   phase_end(p, ENKFMC_PH_ADJ_REGRESS, s);
   phase_begin(p, ENKFMC_PH_ADJ_GATHER, s);
-  hipLaunchKernelGGL(k_adj_ubar_tiles, dim3(nb, (unsigned)max_block_tiles(p)), dim3(64), 0, s, d.blocks, d.row_ptr,
-                     d.col, d.rt_ptr, d.tile_eoff, d.ct_ptr, d.ct_row, d.ct_slot, d.tiles, d.tdiag, d.aux3, d.aux1,
-                     d.aux2, N, d.ubar);
+  const int mtu = max_block_tiles(p);
+  hipLaunchKernelGGL(k_adj_ubar_tiles, dim3(nb * (unsigned)mtu), dim3(64), 0, s, d.blocks, d.row_ptr, d.col,
+                     d.rt_ptr, d.tile_eoff, d.ct_ptr, d.ct_row, d.ct_slot, d.tiles, d.tdiag, d.aux3, d.aux1, d.aux2, N,
+                     mtu, d.ubar);
   hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)((p->n + 3) / 4)), dim3(256), 0, s, d.g2f_ptr, d.g2f, d.ubar, dXa,
                      p->n, N, dXb);
   if (p->m > 0)

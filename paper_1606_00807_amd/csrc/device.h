@@ -91,6 +91,15 @@ __device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G) {
   return x < rm ? x * (q + 1) + s : rm * (q + 1) + (x - rm) * q + s;
 }
 
+// Decode of a one-dimensional launch over (block, tile) pairs, logical index
+// block * per_block + tile, numbered XCD-contiguously: the tiles of one block
+// are neighbouring workgroups on one XCD and share the block's data in its L2.
+__device__ __forceinline__ void block_tile(int per_block, int &blk, int &tile) {
+  const int64_t lg = xcd_contiguous(blockIdx.x, gridDim.x);
+  blk = (int)(lg / per_block);
+  tile = (int)(lg % per_block);
+}
+
 __device__ inline void set_error(int32_t *status, int32_t code, int32_t where) {
   if (atomicCAS(status, 0, code) == 0) atomicExch(status + 1, where);
 }
