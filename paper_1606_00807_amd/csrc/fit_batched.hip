@@ -112,6 +112,7 @@ struct AdjIO {
   double *sb;           // per CSR entry: betabar on entry, s on exit
   double *e1, *e2;      // n_fit x N
   double *lam_row;      // per fit row: its share of dL/dlam
+  double *ebl;          // wavefront LDS (16 kMaxT): epsbar of the row, p-form
 };
 
 // Adjoint pre-pass of row r, before its Gram: eps from the stored
@@ -221,7 +222,9 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   const int q = lane >> 4, c = lane & 15;
   const int m = KF ? N : p;
   double augv[T];   // bordering row: element 16J + c at lane (q = 0, c)
-  if constexpr (ADJ) adj_rhs<T, KF>(lane, r, p, N, U, ldu, uoff, L, tval, lo, adj, augv);
+  // kernel form: eps, epsbar and b in passes of their own; the p-form forms
+  // them inside its Gram loop below
+  if constexpr (ADJ && KF) adj_rhs<T, KF>(lane, r, p, N, U, ldu, uoff, L, tval, lo, adj, augv);
   d4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
@@ -273,15 +276,41 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     double vp[T];
 #pragma unroll
     for (int I = 0; I < T; ++I) vp[I] = 0.0;
+    // adjoint: lane (q, c) holds beta of predecessor 16I + c; at member
+    // k = 4ks + q the 16 lanes of a quarter sum beta_a U[P_a][k], giving
+    // eps_k = u_k - U_P^T beta and epsbar_k = 2 Dbar eps_k / (N-1), and vp[I]
+    // gathers sum_k U[P_{16I+c}][k] epsbar_k for b = betabar - U_P epsbar
+    double bet[T];
+    double Db = 0.0;
+    if constexpr (ADJ) {
+#pragma unroll
+      for (int I = 0; I < T; ++I) bet[I] = 16 * I + c < p ? -tval[lo + 16 * I + c] : 0.0;
+      Db = adj.dbar[r];
+    }
     for (int ks = 0; ks < ksteps; ++ks) {
       double f[T];
 #pragma unroll
       for (int I = 0; I < T; ++I) f[I] = U[base[I] + 4 * ks];
       if constexpr (ADJ) {
+        const int k = 4 * ks + q;
+        const double uk = U[uoff + k];
+        double es = 0.0;
 #pragma unroll
-        for (int I = 0; I < T; ++I)
+        for (int I = 0; I < T; ++I) {
 #pragma unroll
           for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I], f[J], acc[tix<T>(I, J)]);
+          es = fma(bet[I], f[I], es);
+        }
+        es = row16_sum(es);
+        const double nm1 = (double)(N - 1);
+        const double eps = k < N ? uk - es : 0.0;
+        const double eb = 2.0 * Db * eps / nm1;
+        if (c == 0 && k < N) {
+          adj.e1[r * N + k] = eps / nm1;
+          adj.ebl[k] = eb;
+        }
+#pragma unroll
+        for (int I = 0; I < T; ++I) vp[I] = fma(f[I], eb, vp[I]);
       } else {
         const double uk = U[uoff + q + 4 * ks];
 #pragma unroll
@@ -292,7 +321,15 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         }
       }
     }
-    if constexpr (!ADJ) {
+    if constexpr (ADJ) {
+#pragma unroll
+      for (int I = 0; I < T; ++I) {
+        vp[I] += __shfl_xor(vp[I], 16, 64);
+        vp[I] += __shfl_xor(vp[I], 32, 64);
+        const int a = 16 * I + c;
+        augv[I] = (a < p && q == 0) ? adj.sb[lo + a] - vp[I] : 0.0;   // b_a
+      }
+    } else {
 #pragma unroll
       for (int I = 0; I < T; ++I) {
         vp[I] += __shfl_xor(vp[I], 16, 64);
@@ -566,7 +603,8 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         if (q == 0 && k < N) adj.e2[r * N + k] = -(e / nm1 + adj.e2[r * N + k]);
       }
     } else {
-      // same lane per entry as the pre-pass, which stored b there
+      // s overwrites betabar in sb (betabar was read into the right-hand side
+      // before the factorisation)
       double *sl = L.tile;     // s (kMaxP entries)
       for (int ks = 0; 4 * ks < p; ++ks) {
         const int a = 4 * ks + q;
@@ -578,7 +616,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         }
       }
       wave_lds_sync();
-      // e2 = -(U_P^T s/(N-1) + epsbar), epsbar left in e2 by the pre-pass
+      // e2 = -(U_P^T s/(N-1) + epsbar), epsbar left in LDS by the Gram loop
 #pragma unroll
       for (int I = 0; I < kMaxT; ++I) {
         if (16 * I >= N) break;
@@ -587,7 +625,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         for (int a = q; a < p; a += 4) e = fma(sl[a], U[L.pidx[a] * ldu + k], e);
         e += __shfl_xor(e, 16, 64);
         e += __shfl_xor(e, 32, 64);
-        if (q == 0 && k < N) adj.e2[r * N + k] = -(e / nm1 + adj.e2[r * N + k]);
+        if (q == 0 && k < N) adj.e2[r * N + k] = -(e / nm1 + adj.ebl[k]);
       }
     }
     ls = wave_sum(ls);
@@ -635,6 +673,7 @@ __global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_b
     int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, double lam, double *__restrict__ tval,
     AdjIO adj, int32_t *status) {
   __shared__ WaveLds<T> lds[4];
+  __shared__ double ebl[4][16 * kMaxT];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
   if (idx >= nrows) return;
@@ -646,7 +685,9 @@ __global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_b
   const int uoff = fit_glob[r] * ldu;
   for (int k = lane; k < kMaxP + 8; k += 64) L.pidx[k] = k < p ? fit_glob[B.row0 + col[lo + k]] : zrow;
   wave_lds_sync();
-  fit_row<T, KF, true>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, nullptr, status, adj);
+  AdjIO aw = adj;
+  aw.ebl = ebl[wave];
+  fit_row<T, KF, true>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, nullptr, status, aw);
 }
 
 // Adjoint of the regressions without predecessors (eps = u).
