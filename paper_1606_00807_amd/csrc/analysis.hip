@@ -688,10 +688,6 @@ __global__ __launch_bounds__(256) void k_mapback(const TX *__restrict__ Xb, int6
   Xa[idx] = (TO)((double)Xb[g * ld + c] + Z[(int64_t)src[g] * N + c]);
 }
 
-// Largest ring of Z tiles a sweep keeps in LDS (one workgroup's dynamic LDS);
-// plans that need more use the sweep without a ring.
-constexpr size_t kRingMaxBytes = 64 * 1024;
-
 int max_block_tiles(const enkfmc_plan *p) {
   int mx = 0;
   for (const Block &B : p->blocks) mx = B.nrt > mx ? B.nrt : mx;

@@ -86,6 +86,10 @@ inline Dev make_dev(enkfmc_plan *p) {
 // logical workgroups (a bijection on [0, G)): neighbouring rows, which share
 // most of their predecessors' rows of U, then meet in the same L2.
 constexpr int kXcds = 8;
+
+// Largest ring of 16x16 tiles a triangular sweep keeps in LDS (one
+// workgroup's dynamic LDS); plans that need more use the sweeps without one.
+constexpr size_t kRingMaxBytes = 64 * 1024;
 __device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G) {
   const int64_t x = b % kXcds, s = b / kXcds, q = G / kXcds, rm = G % kXcds;
   return x < rm ? x * (q + 1) + s : rm * (q + 1) + (x - rm) * q + s;
