@@ -233,14 +233,19 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   // pidx[k] for k >= p names the all-zero pad row of U, so padded fragments
   // load zeros; the loads of step ks+1 are issued before the MFMAs of ks.
   if (KF) {
-    const int ksteps = (p + 3) >> 2;
+    // An even number of k-steps and no exit inside the loop body: with an exit
+    // between the two halves the compiler copied every accumulator on each
+    // trip and dropped the prefetch.  An odd count gets one step on the zero
+    // pad row, and the prefetch one step past the end also reads pad entries
+    // (pidx holds kMaxP + 8 entries, 4 * 32 + 3 < kMaxP + 8).
+    const int kse = (((p + 3) >> 2) + 1) & ~1;
     double fa[T], fb[T];
     {
       const int off = L.pidx[q] * ldu + c;
 #pragma unroll
       for (int I = 0; I < T; ++I) fa[I] = U[off + 16 * I];
     }
-    for (int ks = 0; ks < ksteps; ks += 2) {
+    for (int ks = 0; ks < kse; ks += 2) {
       const int offb = L.pidx[4 * ks + 4 + q] * ldu + c;
 #pragma unroll
       for (int I = 0; I < T; ++I) fb[I] = U[offb + 16 * I];
@@ -248,7 +253,6 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       for (int I = 0; I < T; ++I)
 #pragma unroll
         for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[I], fa[J], acc[tix<T>(I, J)]);
-      if (ks + 1 >= ksteps) break;
       const int offa = L.pidx[4 * ks + 8 + q] * ldu + c;
 #pragma unroll
       for (int I = 0; I < T; ++I) fa[I] = U[offa + 16 * I];
