@@ -249,17 +249,21 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       const int offb = L.pidx[4 * ks + 4 + q] * ldu + c;
 #pragma unroll
       for (int I = 0; I < T; ++I) fb[I] = U[offb + 16 * I];
+      __builtin_amdgcn_sched_barrier(0);   // keep each half's loads ahead of the other half's products
 #pragma unroll
       for (int I = 0; I < T; ++I)
 #pragma unroll
         for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[I], fa[J], acc[tix<T>(I, J)]);
+      __builtin_amdgcn_sched_barrier(0);
       const int offa = L.pidx[4 * ks + 8 + q] * ldu + c;
 #pragma unroll
       for (int I = 0; I < T; ++I) fa[I] = U[offa + 16 * I];
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int I = 0; I < T; ++I)
 #pragma unroll
         for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fb[I], fb[J], acc[tix<T>(I, J)]);
+      __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (!ADJ) {
 #pragma unroll
