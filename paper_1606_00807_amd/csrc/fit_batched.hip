@@ -521,18 +521,30 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     // beta_a = sum_k U[P_a][k] w_k: lane (q, c) loads members 16I + c of
     // predecessor 4ks + q (the Gram's coalesced fragments); the 16 lanes of
     // each quarter then add their partial sums.
+    // Four k-steps per trip, their loads issued together (the steps are
+    // independent; one at a time each waited for its own loads).  Steps past
+    // the last read the zero pad row (pidx holds kMaxP + 8 entries).
     double wv[T];
 #pragma unroll
     for (int I = 0; I < T; ++I) wv[I] = y[16 * I + c];
-    const int ksteps = (p + 3) >> 2;
-    for (int ks = 0; ks < ksteps; ++ks) {
-      const int a = 4 * ks + q;
-      const int off = L.pidx[a] * ldu + c;
-      double b = 0.0;
+    const int ks4 = (((p + 3) >> 2) + 3) & ~3;
+    for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
+      double f[4][T];
 #pragma unroll
-      for (int I = 0; I < T; ++I) b = fma(U[off + 16 * I], wv[I], b);
-      b = row16_sum(b);
-      if (c == 0 && a < p) tval[lo + a] = -b;
+      for (int u = 0; u < 4; ++u) {
+        const int off = L.pidx[4 * (ks0 + u) + q] * ldu + c;
+#pragma unroll
+        for (int I = 0; I < T; ++I) f[u][I] = U[off + 16 * I];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int a = 4 * (ks0 + u) + q;
+        double b = 0.0;
+#pragma unroll
+        for (int I = 0; I < T; ++I) b = fma(f[u][I], wv[I], b);
+        b = row16_sum(b);
+        if (c == 0 && a < p) tval[lo + a] = -b;
+      }
     }
     if (q == 0) {
 #pragma unroll
