@@ -134,7 +134,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the sub-domains of this workload would be sharded in latitude bands "
-              "across GPUs, but this build has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+              "across GPUs, but the library has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
