@@ -470,7 +470,11 @@ __global__ __launch_bounds__(64) void k_dual_Q(const Block *__restrict__ blocks,
 
 // G = D (F Q) of row tile R (or D (V - F Q) with V given), written into the
 // output rows that the forward sweep then solves in place.  One wavefront per
-// (block, row tile); it loops over the 16-member column tiles.
+// (block, row tile).  Each F fragment it loads feeds up to kGTiles 16-member
+// column tiles at once, so F_R is read once per kGTiles member tiles (the
+// launch is bound by HBM traffic, most of it re-reads of F).
+constexpr int kGTiles = 5;
+
 __global__ __launch_bounds__(64) void k_dual_G(const Block *__restrict__ blocks, const int32_t *__restrict__ ot_jmax,
                                                const double *__restrict__ F, const double *__restrict__ Q,
                                                const double *__restrict__ dvec, const double *__restrict__ V, int N,
@@ -488,27 +492,40 @@ __global__ __launch_bounds__(64) void k_dual_G(const Block *__restrict__ blocks,
     const int row = 16 * R + 4 * r + q;
     dd[r] = row < B.n ? dvec[B.row0 + row] : 0.0;
   }
-  for (int cc = 0; 16 * cc < N; ++cc) {
-    const int colj = 16 * cc + c;
-    const bool colok = colj < N;
-    const int coll = colok ? colj : 0;
-    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+  const int ng = (N + 15) >> 4;
+  for (int g0 = 0; g0 < ng; g0 += kGTiles) {
+    const int ngc = ng - g0 < kGTiles ? ng - g0 : kGTiles;
+    d4 acc[kGTiles];
+#pragma unroll
+    for (int g = 0; g < kGTiles; ++g) acc[g] = d4{0.0, 0.0, 0.0, 0.0};
     for (int t = 0; t < (ldf >> 4); ++t) {
       if (ot_jmax[B.ot0 + t] < 16 * R) continue;   // F_R is zero in these 16 columns
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int ks = 4 * t + kk;
-        const double bq = Qb[(int64_t)(4 * ks + q) * N + coll];
-        acc = mfma64(Fr[4 * ks], colok ? bq : 0.0, acc);
+        const double fa = Fr[4 * ks];
+        const double *qr = Qb + (int64_t)(4 * ks + q) * N;
+#pragma unroll
+        for (int g = 0; g < kGTiles; ++g) {
+          if (g < ngc) {
+            const int colj = 16 * (g0 + g) + c;
+            const double bq = qr[colj < N ? colj : 0];   // clamped: the address stays inside the row
+            acc[g] = mfma64(fa, colj < N ? bq : 0.0, acc[g]);
+          }
+        }
       }
     }
-    if (!colok) continue;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * R + 4 * r + q;
-      if (row < B.n) {
-        const int64_t o = (B.row0 + row) * N + colj;
-        G[o] = V ? dd[r] * (V[o] - acc[r]) : dd[r] * acc[r];
+    for (int g = 0; g < kGTiles; ++g) {
+      const int colj = 16 * (g0 + g) + c;
+      if (g >= ngc || colj >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * R + 4 * r + q;
+        if (row < B.n) {
+          const int64_t o = (B.row0 + row) * N + colj;
+          G[o] = V ? dd[r] * (V[o] - acc[g][r]) : dd[r] * acc[g][r];
+        }
       }
     }
   }
