@@ -654,7 +654,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 }
 
 // waves per SIMD each kernel is compiled for (register budget 512 / occupancy)
-constexpr int occupancy_for(int T, bool KF) { return T <= 2 ? 4 : (T == 3 ? (KF ? 4 : 3) : (T == 4 ? 3 : 2)); }
+constexpr int occupancy_for(int T, bool KF) { return T <= 2 ? 4 : (T == 3 ? 4 : (T == 4 ? 3 : 2)); }
 
 template <int T, bool KF>
 __global__ __launch_bounds__(256, occupancy_for(T, KF)) void k_fit_batched(
