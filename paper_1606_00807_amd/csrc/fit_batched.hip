@@ -113,11 +113,14 @@ struct AdjIO {
   double *ebl;          // wavefront LDS (16 kMaxT): epsbar of the row, p-form
 };
 
-// Adjoint pre-pass of row r, before its Gram: eps from the stored
-// coefficients, epsbar, b = betabar - U_P epsbar, and the right-hand side
-// (b, or U_P^T b in the kernel form) in the bordering row.  Leaves e1 = eps/(N-1),
-// e2 = epsbar and sb = b in global memory for the post-pass.
-template <int T, bool KF>
+// Adjoint pre-pass of a kernel-form row r, before its Gram: eps from the
+// stored coefficients, epsbar, b = betabar - U_P epsbar, and the right-hand
+// side U_P^T b in the bordering row.  Leaves e1 = eps/(N-1), e2 = epsbar and
+// sb = b in global memory for the post-pass.  Both passes over U_P load the
+// Gram's fragments (members 16I + c of predecessor 4ks + q), four k-steps of
+// loads at a time; steps past the last read the zero pad row (the pidx index
+// stays below 4 * 32 < kMaxP + 8).
+template <int T>
 __device__ __forceinline__ void adj_rhs(const int lane, const int64_t r, const int p, const int N,
                                         const double *__restrict__ U, const int ldu, const int uoff, WaveLds<T> &L,
                                         const double *__restrict__ tval, const int64_t lo, const AdjIO &adj,
@@ -125,22 +128,39 @@ __device__ __forceinline__ void adj_rhs(const int lane, const int64_t r, const i
   const int q = lane >> 4, c = lane & 15;
   const double nm1 = (double)(N - 1);
   const double Db = adj.dbar[r];
-  double *bl = L.tile;             // beta, then b (kMaxP entries)
+  double *bl = L.tile;             // beta (kMaxP entries)
   double *el = L.tile + kMaxP;     // epsbar (16 * kMaxT entries)
   for (int a = lane; a < kMaxP; a += 64) bl[a] = a < p ? -tval[lo + a] : 0.0;
   wave_lds_sync();
-  // eps_k = u_k - sum_a beta_a U[P_a][k]: lane (q, c) takes member 16I + c and
-  // predecessors a = q mod 4; the partial sums are then added across q.
+  const int ks4 = (((p + 3) >> 2) + 3) & ~3;
+  // eps_k = u_k - sum_a beta_a U[P_a][k]: lane (q, c) sums members 16I + c
+  // over predecessors a = q mod 4; the partial sums are then added across q.
+  double e[T];
 #pragma unroll
-  for (int I = 0; I < kMaxT; ++I) {
-    if (16 * I >= N) break;
+  for (int I = 0; I < T; ++I) e[I] = 0.0;
+  for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
+    double f[4][T], bb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int a = 4 * (ks0 + u) + q;
+      const int off = L.pidx[a] * ldu + c;
+      bb[u] = bl[a];
+#pragma unroll
+      for (int I = 0; I < T; ++I) f[u][I] = U[off + 16 * I];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int I = 0; I < T; ++I) e[I] = fma(bb[u], f[u][I], e[I]);
+  }
+#pragma unroll
+  for (int I = 0; I < T; ++I) {
+    double es = e[I];
+    es += __shfl_xor(es, 16, 64);
+    es += __shfl_xor(es, 32, 64);
     const int k = 16 * I + c;
-    double e = 0.0;
-    for (int a = q; a < p; a += 4) e = fma(bl[a], U[L.pidx[a] * ldu + k], e);
-    e += __shfl_xor(e, 16, 64);
-    e += __shfl_xor(e, 32, 64);
     const bool ok = k < N;
-    const double eps = ok ? U[uoff + k] - e : 0.0;
+    const double eps = ok ? U[uoff + k] - es : 0.0;
     const double eb = 2.0 * Db * eps / nm1;
     if (q == 0) {
       el[k] = eb;
@@ -151,62 +171,41 @@ __device__ __forceinline__ void adj_rhs(const int lane, const int64_t r, const i
     }
   }
   wave_lds_sync();
-  // b_a = betabar_a - sum_k U[P_a][k] epsbar_k: lane (q, c) loads members
-  // 16I + c of predecessor 4ks + q and the 16 lanes of each quarter add up.
-  // The kernel form accumulates (U_P^T b)_k from the same fragments.
-  const int TN = (N + 15) >> 4;
-  double ev[kMaxT];
+  // b_a = betabar_a - sum_k U[P_a][k] epsbar_k (the 16 lanes of each quarter
+  // add up), and (U_P^T b)_k accumulated from the same fragments
+  double ev[T];
 #pragma unroll
-  for (int I = 0; I < kMaxT; ++I) ev[I] = I < TN ? el[16 * I + c] : 0.0;
-  const int ksteps = (p + 3) >> 2;
-  if constexpr (KF) {
-    double tacc[T];
+  for (int I = 0; I < T; ++I) ev[I] = el[16 * I + c];
+  double tacc[T];
 #pragma unroll
-    for (int I = 0; I < T; ++I) tacc[I] = 0.0;
-    for (int ks = 0; ks < ksteps; ++ks) {
-      const int a = 4 * ks + q;
-      const int off = L.pidx[a] * ldu + c;
-      double f[T], sm = 0.0;
+  for (int I = 0; I < T; ++I) tacc[I] = 0.0;
+  for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
+    double f[4][T];
 #pragma unroll
-      for (int I = 0; I < T; ++I) {
-        f[I] = U[off + 16 * I];
-        sm = fma(f[I], ev[I], sm);
-      }
+    for (int u = 0; u < 4; ++u) {
+      const int off = L.pidx[4 * (ks0 + u) + q] * ldu + c;
+#pragma unroll
+      for (int I = 0; I < T; ++I) f[u][I] = U[off + 16 * I];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int a = 4 * (ks0 + u) + q;
+      double sm = 0.0;
+#pragma unroll
+      for (int I = 0; I < T; ++I) sm = fma(f[u][I], ev[I], sm);
       sm = row16_sum(sm);
       const double b = a < p ? adj.sb[lo + a] - sm : 0.0;
       if (c == 0 && a < p) adj.sb[lo + a] = b;
 #pragma unroll
-      for (int I = 0; I < T; ++I) tacc[I] = fma(f[I], b, tacc[I]);
+      for (int I = 0; I < T; ++I) tacc[I] = fma(f[u][I], b, tacc[I]);
     }
+  }
 #pragma unroll
-    for (int I = 0; I < T; ++I) {
-      double e = tacc[I];
-      e += __shfl_xor(e, 16, 64);
-      e += __shfl_xor(e, 32, 64);
-      augv[I] = (q == 0 && 16 * I + c < N) ? e : 0.0;
-    }
-  } else {
-    for (int ks = 0; ks < ksteps; ++ks) {
-      const int a = 4 * ks + q;
-      const int off = L.pidx[a] * ldu + c;
-      double sm = 0.0;
-#pragma unroll
-      for (int I = 0; I < kMaxT; ++I)
-        if (I < TN) sm = fma(U[off + 16 * I], ev[I], sm);
-      sm = row16_sum(sm);
-      if (c == 0 && a < p) {
-        const double b = adj.sb[lo + a] - sm;
-        adj.sb[lo + a] = b;
-        bl[a] = b;
-      }
-    }
-    // entries a >= p of bl still hold the zero padding written above
-    wave_lds_sync();
-#pragma unroll
-    for (int g = 0; g < T; ++g) {   // p <= 16 T
-      const int a = 16 * g + c;
-      augv[g] = (q == 0 && a < p) ? bl[a] : 0.0;
-    }
+  for (int I = 0; I < T; ++I) {
+    double t = tacc[I];
+    t += __shfl_xor(t, 16, 64);
+    t += __shfl_xor(t, 32, 64);
+    augv[I] = (q == 0 && 16 * I + c < N) ? t : 0.0;
   }
   wave_lds_sync();
 }
@@ -222,7 +221,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   double augv[T];   // bordering row: element 16J + c at lane (q = 0, c)
   // kernel form: eps, epsbar and b in passes of their own; the p-form forms
   // them inside its Gram loop below
-  if constexpr (ADJ && KF) adj_rhs<T, KF>(lane, r, p, N, U, ldu, uoff, L, tval, lo, adj, augv);
+  if constexpr (ADJ && KF) adj_rhs<T>(lane, r, p, N, U, ldu, uoff, L, tval, lo, adj, augv);
   d4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
@@ -593,24 +592,31 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         wv[I] = y[16 * I + c];
         gacc[I] = 0.0;
       }
-      const int ksteps = (p + 3) >> 2;
-      for (int ks = 0; ks < ksteps; ++ks) {
-        const int a = 4 * ks + q;
-        const int off = L.pidx[a] * ldu + c;
-        double f[T], b = 0.0;
+      // four k-steps of fragment loads at a time (pad row past the last)
+      const int ks4 = (((p + 3) >> 2) + 3) & ~3;
+      for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
+        double f[4][T];
 #pragma unroll
-        for (int I = 0; I < T; ++I) {
-          f[I] = U[off + 16 * I];
-          b = fma(f[I], wv[I], b);
-        }
-        b = row16_sum(b);
-        const double sv = a < p ? (nm1 / mu) * (adj.sb[lo + a] - b) : 0.0;
-        if (c == 0 && a < p) {
-          adj.sb[lo + a] = sv;
-          ls = fma(sv, tval[lo + a], ls);
+        for (int u = 0; u < 4; ++u) {
+          const int off = L.pidx[4 * (ks0 + u) + q] * ldu + c;
+#pragma unroll
+          for (int I = 0; I < T; ++I) f[u][I] = U[off + 16 * I];
         }
 #pragma unroll
-        for (int I = 0; I < T; ++I) gacc[I] = fma(f[I], sv, gacc[I]);
+        for (int u = 0; u < 4; ++u) {
+          const int a = 4 * (ks0 + u) + q;
+          double b = 0.0;
+#pragma unroll
+          for (int I = 0; I < T; ++I) b = fma(f[u][I], wv[I], b);
+          b = row16_sum(b);
+          const double sv = a < p ? (nm1 / mu) * (adj.sb[lo + a] - b) : 0.0;
+          if (c == 0 && a < p) {
+            adj.sb[lo + a] = sv;
+            ls = fma(sv, tval[lo + a], ls);
+          }
+#pragma unroll
+          for (int I = 0; I < T; ++I) gacc[I] = fma(f[u][I], sv, gacc[I]);
+        }
       }
 #pragma unroll
       for (int I = 0; I < T; ++I) {
@@ -633,17 +639,40 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
           ls = fma(sv, tval[lo + a], ls);
         }
       }
+      // s is zero past p, up to the last k-step batch
+      const int ks4 = (((p + 3) >> 2) + 3) & ~3;
+      for (int a = p + lane; a < 4 * ks4; a += 64) sl[a] = 0.0;
       wave_lds_sync();
-      // e2 = -(U_P^T s/(N-1) + epsbar), epsbar left in LDS by the Gram loop
+      // e2 = -(U_P^T s/(N-1) + epsbar), epsbar left in LDS by the Gram loop;
+      // lane (q, c) sums members 16I + c over predecessors a = q mod 4, four
+      // k-steps of loads at a time (pad row past p, columns 16I + c < ldu)
+      const int nt = (N + 15) >> 4;
+      double e[kMaxT];
+#pragma unroll
+      for (int I = 0; I < kMaxT; ++I) e[I] = 0.0;
+      for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
+        double f[4][kMaxT], sv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int a = 4 * (ks0 + u) + q;
+          const int off = L.pidx[a] * ldu + c;
+          sv[u] = sl[a];
+#pragma unroll
+          for (int I = 0; I < kMaxT; ++I) f[u][I] = I < nt ? U[off + 16 * I] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int I = 0; I < kMaxT; ++I) e[I] = fma(sv[u], f[u][I], e[I]);
+      }
 #pragma unroll
       for (int I = 0; I < kMaxT; ++I) {
-        if (16 * I >= N) break;
+        if (I >= nt) break;
+        double es = e[I];
+        es += __shfl_xor(es, 16, 64);
+        es += __shfl_xor(es, 32, 64);
         const int k = 16 * I + c;
-        double e = 0.0;
-        for (int a = q; a < p; a += 4) e = fma(sl[a], U[L.pidx[a] * ldu + k], e);
-        e += __shfl_xor(e, 16, 64);
-        e += __shfl_xor(e, 32, 64);
-        if (q == 0 && k < N) adj.e2[r * N + k] = -(e / nm1 + adj.ebl[k]);
+        if (q == 0 && k < N) adj.e2[r * N + k] = -(es / nm1 + adj.ebl[k]);
       }
     }
     ls = wave_sum(ls);
