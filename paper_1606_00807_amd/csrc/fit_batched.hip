@@ -271,7 +271,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       }
     }
   } else {
-    // lane (q, c) also sums u_k U[P_{16I+c}][k] over members k = q mod 4.
+    // lane (q, c) also sums u_k U[P_{16I+c}][k] over the members it loads.
     // (Single-buffered: a double-buffered form of this loop was miscompiled,
     // its live MFMA accumulators being reused as load destinations.)
     const int ksteps = (N + 3) >> 2;
@@ -292,11 +292,34 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       for (int I = 0; I < T; ++I) bet[I] = 16 * I + c < p ? -tval[lo + 16 * I + c] : 0.0;
       Db = adj.dbar[r];
     }
-    for (int ks = 0; ks < ksteps; ++ks) {
-      double f[T];
+    if constexpr (!ADJ) {
+      // One 16-byte load per tile brings members 8ks + 2q and 8ks + 2q + 1;
+      // they form two consecutive k-steps of the product (the sum over
+      // members does not depend on which k-step takes which member).
+      // 8 * ks2 <= ldu, whose columns past N are zero.
+      const int ks2 = (N + 7) >> 3;
+      for (int ks = 0; ks < ks2; ++ks) {
+        double2 f[T];
 #pragma unroll
-      for (int I = 0; I < T; ++I) f[I] = U[base[I] + 4 * ks];
-      if constexpr (ADJ) {
+        for (int I = 0; I < T; ++I) f[I] = *(const double2 *)&U[base[I] + q + 8 * ks];
+        const double2 uk = *(const double2 *)&U[uoff + 2 * q + 8 * ks];
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I].x, f[J].x, acc[tix<T>(I, J)]);
+#pragma unroll
+        for (int I = 0; I < T; ++I) {
+#pragma unroll
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I].y, f[J].y, acc[tix<T>(I, J)]);
+          vp[I] = fma(f[I].x, uk.x, vp[I]);
+          vp[I] = fma(f[I].y, uk.y, vp[I]);
+        }
+      }
+    } else {
+      for (int ks = 0; ks < ksteps; ++ks) {
+        double f[T];
+#pragma unroll
+        for (int I = 0; I < T; ++I) f[I] = U[base[I] + 4 * ks];
         const int k = 4 * ks + q;
         const double uk = U[uoff + k];
         double es = 0.0;
@@ -316,14 +339,6 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         }
 #pragma unroll
         for (int I = 0; I < T; ++I) vp[I] = fma(f[I], eb, vp[I]);
-      } else {
-        const double uk = U[uoff + q + 4 * ks];
-#pragma unroll
-        for (int I = 0; I < T; ++I) {
-#pragma unroll
-          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I], f[J], acc[tix<T>(I, J)]);
-          vp[I] = fma(f[I], uk, vp[I]);
-        }
       }
     }
     if constexpr (ADJ) {
