@@ -47,7 +47,6 @@ constexpr int kTileLd = 17;       // padded row stride of the transpose buffer
 template <int T>
 struct WaveLds {                  // wavefront-private LDS (doubles unless noted)
   int pidx[kMaxP + 8];            // global rows of the predecessors, pad row beyond p
-  double col[16 * (T + 1)];
   double vec[16 * (T + 1)];
   double dinv[16 * T];            // 1 / L_kk of the factor
   double tile[T * 16 * kTileLd];
@@ -102,6 +101,81 @@ __device__ __forceinline__ double row16_sum(double v) {
   v += dpp_d<0x141>(v);   // row_half_mirror
   v += dpp_d<0x140>(v);   // row_mirror
   return v;
+}
+
+// Lane N of each row of 16 lanes, given to the whole row (DPP row_newbcast).
+template <int N>
+__device__ __forceinline__ double row_bcast(double v) { return dpp_d<0x150 + N>(v); }
+
+// Row Q of the wavefront (lanes 16Q..16Q+15), given to all four rows, lane
+// 16q + c receiving lane 16Q + c.  The 16-lane swap of a register with itself
+// leaves rows (0,0,2,2) in its first result and (1,1,3,3) in its second; the
+// 32-lane swap of either with itself then leaves the low pair's row in its
+// first result and the high pair's in its second.
+template <int Q>
+__device__ __forceinline__ unsigned quarter_bcast_u(unsigned x) {
+  const auto a = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  const unsigned t = (Q & 1) ? a[1] : a[0];
+  const auto b = __builtin_amdgcn_permlane32_swap(t, t, false, false);
+  return (Q & 2) ? b[1] : b[0];
+}
+template <int Q>
+__device__ __forceinline__ double quarter_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = quarter_bcast_u<Q>((unsigned)(b & 0xffffffffll));
+  const unsigned hi = quarter_bcast_u<Q>((unsigned)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | lo);
+}
+
+// Column K of a diagonal tile's elimination (step 3 of fit_row), all in
+// registers.  Lane (q, c) holds a[4rr + q][c] in ajj[rr], E[4rr + q][c] in
+// eid[rr] and, at q = 0, the bordering row's entry c in ag.  a[i][K] for the
+// lane's rows comes from lane (q, K) of its own row of 16; a[c][K] is taken as
+// a[K][c] (lane (K mod 4, c), register K / 4), which the symmetric updates of
+// the columns right of K keep equal to it up to rounding.  piv enters as the
+// pivot of column K and leaves as that of column K + 1 (a look-ahead on
+// a[K+1][K] and a[K+1][K+1] only); 1/sqrt(piv) is kept by lane c = K.
+template <int K>
+__device__ __forceinline__ void elim_col(const int c, const bool below, d4 &ajj, d4 &eid, double &ag,
+                                         double &piv, double &myinv) {
+  const double inv = rsqrt_nr(piv);
+  if (c == K) myinv = inv;
+  const double ab = readlane_d(ag, K) * inv;   // L^-1 of the bordering entry K
+  if constexpr (K + 1 < 16) {
+    constexpr int q1 = (K + 1) & 3, r1 = (K + 1) >> 2;
+    const double lnext = readlane_d(ajj[r1], 16 * q1 + K) * inv;
+    const double anext = readlane_d(ajj[r1], 16 * q1 + K + 1);
+    piv = fma(-lnext, lnext, anext);
+  }
+  const double colv = quarter_bcast<K & 3>(ajj[K >> 2]);
+  const double cv1 = c > K ? colv * inv : 0.0;   // L[c][K]
+  const double cv2 = cv1 * inv;
+  d4 rowv;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) rowv[rr] = row_bcast<K>(ajj[rr]);
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) ajj[rr] = fma(-rowv[rr], cv2, ajj[rr]);
+  if (below) {
+    d4 rowe;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) rowe[rr] = row_bcast<K>(eid[rr]);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) eid[rr] = fma(-rowe[rr], cv2, eid[rr]);
+  }
+  ag = c == K ? ab : fma(-ab, cv1, ag);
+  // one scheduling region per column: interleaving columns raised the
+  // register demand past the budget
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Columns K..15; false at the first pivot that is not positive (or NaN).
+template <int K>
+__device__ __forceinline__ bool elim_cols(const int c, const bool below, d4 &ajj, d4 &eid, double &ag,
+                                          double &piv, double &myinv) {
+  if (!(piv > 0.0)) return false;
+  elim_col<K>(c, below, ajj, eid, ag, piv, myinv);
+  if constexpr (K + 1 < 16) return elim_cols<K + 1>(c, below, ajj, eid, ag, piv, myinv);
+  return true;
 }
 
 // Arrays of the adjoint pass.
@@ -372,11 +446,11 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   // Per panel J: the 16 columns of the diagonal tile are eliminated one at a
   // time, carrying an identity tile E along as extra rows, so that E ends as
   // L_JJ^-T; the tiles below then follow as L_IJ = A_IJ L_JJ^-T by MFMA.
-  // L.col holds column k of the diagonal tile at 16J + 4q + rr (row 4rr + q),
-  // that of E at 16J + 16 + 4q + rr, and the bordering row's entry at 16T.
-  // Columns stay unscaled during the elimination: column k is broadcast as is
-  // and the update uses a[i][k] a[j][k] / piv_k.  At the end each column c is
-  // scaled once by its 1/L_cc, which also turns its final pivot into L_cc.
+  // Each column's values reach the other lanes by cross-lane moves
+  // (elim_col).  Columns stay unscaled during the elimination: the update uses
+  // a[i][k] a[j][k] / piv_k.  At the end each column c is scaled once by its
+  // 1/L_cc, which also turns its final pivot into L_cc.  A pivot that is not
+  // positive (or NaN) ends the row with an error.
 #pragma unroll
   for (int J = 0; J < T; ++J) {
     const bool below = J + 1 < T;
@@ -385,55 +459,14 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     for (int rr = 0; rr < 4; ++rr) eid[rr] = (4 * rr + q == c) ? 1.0 : 0.0;
     // pivot of the panel's first column (after the trailing updates)
     double piv = readlane_d(acc[tix<T>(J, J)][0], 0);
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      if (!(piv > 0.0)) {
-        if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
-        return;
-      }
-      const double inv = rsqrt_nr(piv);
-      if (lane == 0) L.dinv[16 * J + kk] = inv;
-      if (c == kk) {
-        *(d4 *)&L.col[16 * J + 4 * q] = acc[tix<T>(J, J)];
-        if (below) *(d4 *)&L.col[16 * J + 16 + 4 * q] = eid;
-        if (q == 0) {
-          augv[J] *= inv;
-          L.col[16 * T] = augv[J];
-        }
-      }
-      // lookahead: the next pivot only needs a[k+1][k] and the not yet updated
-      // a[k+1][k+1]; computing it here takes the reciprocal square root off the
-      // path through the column broadcast
-      if (kk + 1 < 16) {
-        const int q1 = (kk + 1) & 3, r1 = (kk + 1) >> 2;
-        const double lnext = readlane_d(acc[tix<T>(J, J)][r1], 16 * q1 + kk) * inv;
-        const double anext = readlane_d(acc[tix<T>(J, J)][r1], 16 * q1 + kk + 1);
-        piv = fma(-lnext, lnext, anext);
-      }
-      wave_lds_sync();
-      const double colv = L.col[16 * J + 4 * (c & 3) + (c >> 2)];
-      const double cv1 = c > kk ? colv * inv : 0.0;   // L[16J + c][k]
-      const double cv2 = cv1 * inv;
-      {
-        const d4 rowv = *(const d4 *)&L.col[16 * J + 4 * q];
-        d4 v = acc[tix<T>(J, J)];
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) v[rr] = fma(-rowv[rr], cv2, v[rr]);
-        acc[tix<T>(J, J)] = v;
-      }
-      if (below) {
-        const d4 rowe = *(const d4 *)&L.col[16 * J + 16 + 4 * q];
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) eid[rr] = fma(-rowe[rr], cv2, eid[rr]);
-      }
-      augv[J] = fma(-L.col[16 * T], cv1, augv[J]);
-      wave_lds_sync();
+    double myinv = 0.0;
+    if (!elim_cols<0>(c, below, acc[tix<T>(J, J)], eid, augv[J], piv, myinv)) {
+      if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
+      return;
     }
-    {
-      const double myinv = L.dinv[16 * J + c];
-      acc[tix<T>(J, J)] *= myinv;
-      eid *= myinv;   // L_JJ^-T; the accumulator layout is the B operand layout
-    }
+    if (q == 0) L.dinv[16 * J + c] = myinv;
+    acc[tix<T>(J, J)] *= myinv;
+    eid *= myinv;   // L_JJ^-T; the accumulator layout is the B operand layout
     if (below) {
       // L_IJ = A_IJ L_JJ^-T, the A operand transposed through LDS
 #pragma unroll
