@@ -103,33 +103,35 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
-// Lane N of each row of 16 lanes, given to the whole row (DPP row_newbcast).
+// Lane N of each row of 16 lanes, given to the whole row (DPP row_newbcast,
+// one 64-bit move).
 template <int N>
-__device__ __forceinline__ double row_bcast(double v) { return dpp_d<0x150 + N>(v); }
+__device__ __forceinline__ double row_bcast(double v) {
+  return __longlong_as_double(__builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x150 + N, 0xf, 0xf, true));
+}
 
 // Row Q of the wavefront (lanes 16Q..16Q+15), given to all four rows, lane
-// 16q + c receiving lane 16Q + c.  The 16-lane swap of a register with itself
-// leaves rows (0,0,2,2) in its first result and (1,1,3,3) in its second; the
-// 32-lane swap of either with itself then leaves the low pair's row in its
-// first result and the high pair's in its second.
-template <int Q>
-__device__ __forceinline__ unsigned quarter_bcast_u(unsigned x) {
-  const auto a = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-  const unsigned t = (Q & 1) ? a[1] : a[0];
-  const auto b = __builtin_amdgcn_permlane32_swap(t, t, false, false);
-  return (Q & 2) ? b[1] : b[0];
-}
+// 16q + c receiving lane 16Q + c.  With rows written (r0, r1, r2, r3): the
+// 16-lane swap of the low and high words (lo, hi) leaves (lo0, hi0, lo2, hi2)
+// in its first result and (lo1, hi1, lo3, hi3) in its second; the 32-lane swap
+// of one of them with itself leaves (loQ, hiQ, loQ, hiQ) in one result; the
+// 16-lane swap of that with itself leaves loQ in all rows of its first result
+// and hiQ in all rows of its second.
 template <int Q>
 __device__ __forceinline__ double quarter_bcast(double v) {
   const long long b = __double_as_longlong(v);
-  const unsigned lo = quarter_bcast_u<Q>((unsigned)(b & 0xffffffffll));
-  const unsigned hi = quarter_bcast_u<Q>((unsigned)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | lo);
+  const auto s1 = __builtin_amdgcn_permlane16_swap((unsigned)(b & 0xffffffffll), (unsigned)(b >> 32), false, false);
+  const unsigned t = (Q & 1) ? s1[1] : s1[0];
+  const auto s2 = __builtin_amdgcn_permlane32_swap(t, t, false, false);
+  const unsigned u = (Q & 2) ? s2[1] : s2[0];
+  const auto s3 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  return __longlong_as_double(((long long)s3[1] << 32) | s3[0]);
 }
 
 // Column K of a diagonal tile's elimination (step 3 of fit_row), all in
 // registers.  Lane (q, c) holds a[4rr + q][c] in ajj[rr], E[4rr + q][c] in
-// eid[rr] and, at q = 0, the bordering row's entry c in ag.  a[i][K] for the
+// eid[rr] and, at q = 0, the bordering row's entry c in ag (left unscaled,
+// like the columns).  a[i][K] for the
 // lane's rows comes from lane (q, K) of its own row of 16; a[c][K] is taken as
 // a[K][c] (lane (K mod 4, c), register K / 4), which the symmetric updates of
 // the columns right of K keep equal to it up to rounding.  piv enters as the
@@ -140,7 +142,7 @@ __device__ __forceinline__ void elim_col(const int c, const bool below, d4 &ajj,
                                          double &piv, double &myinv) {
   const double inv = rsqrt_nr(piv);
   if (c == K) myinv = inv;
-  const double ab = readlane_d(ag, K) * inv;   // L^-1 of the bordering entry K
+  const double ab = row_bcast<K>(ag) * inv;    // scaled bordering entry K (at q = 0)
   if constexpr (K + 1 < 16) {
     constexpr int q1 = (K + 1) & 3, r1 = (K + 1) >> 2;
     const double lnext = readlane_d(ajj[r1], 16 * q1 + K) * inv;
@@ -162,10 +164,7 @@ __device__ __forceinline__ void elim_col(const int c, const bool below, d4 &ajj,
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) eid[rr] = fma(-rowe[rr], cv2, eid[rr]);
   }
-  ag = c == K ? ab : fma(-ab, cv1, ag);
-  // one scheduling region per column: interleaving columns raised the
-  // register demand past the budget
-  __builtin_amdgcn_sched_barrier(0);
+  ag = fma(-ab, cv1, ag);   // entries c <= K stay as they are (cv1 = 0)
 }
 
 // Columns K..15; false at the first pivot that is not positive (or NaN).
@@ -465,6 +464,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       return;
     }
     if (q == 0) L.dinv[16 * J + c] = myinv;
+    augv[J] *= myinv;
     acc[tix<T>(J, J)] *= myinv;
     eid *= myinv;   // L_JJ^-T; the accumulator layout is the B operand layout
     if (below) {
