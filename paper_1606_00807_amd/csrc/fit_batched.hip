@@ -48,7 +48,6 @@ template <int T>
 struct WaveLds {                  // wavefront-private LDS (doubles unless noted)
   int pidx[kMaxP + 8];            // global rows of the predecessors, pad row beyond p
   double vec[16 * (T + 1)];
-  double dinv[16 * T];            // 1 / L_kk of the factor
   double tile[T * 16 * kTileLd];
 };
 
@@ -128,6 +127,26 @@ __device__ __forceinline__ double quarter_bcast(double v) {
   return __longlong_as_double(((long long)s3[1] << 32) | s3[0]);
 }
 
+// Sum over the four rows of 16 lanes (lanes c, c + 16, c + 32, c + 48), each
+// of them receiving it.  Swapping a register with itself across 16 lanes
+// leaves rows (0, 0, 2, 2) and (1, 1, 3, 3), so their sum holds r0 + r1 and
+// r2 + r3; the 32-lane swap of that leaves (0, 1, 0, 1) and (2, 3, 2, 3).
+__device__ __forceinline__ double pair_sum16(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned l = (unsigned)(b & 0xffffffffll), h = (unsigned)(b >> 32);
+  const auto sl = __builtin_amdgcn_permlane16_swap(l, l, false, false);
+  const auto sh = __builtin_amdgcn_permlane16_swap(h, h, false, false);
+  return __longlong_as_double(((long long)sh[0] << 32) | sl[0]) + __longlong_as_double(((long long)sh[1] << 32) | sl[1]);
+}
+__device__ __forceinline__ double pair_sum32(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned l = (unsigned)(b & 0xffffffffll), h = (unsigned)(b >> 32);
+  const auto sl = __builtin_amdgcn_permlane32_swap(l, l, false, false);
+  const auto sh = __builtin_amdgcn_permlane32_swap(h, h, false, false);
+  return __longlong_as_double(((long long)sh[0] << 32) | sl[0]) + __longlong_as_double(((long long)sh[1] << 32) | sl[1]);
+}
+__device__ __forceinline__ double quarter_sum(double v) { return pair_sum32(pair_sum16(v)); }
+
 // Column K of a diagonal tile's elimination (step 3 of fit_row), all in
 // registers.  Lane (q, c) holds a[4rr + q][c] in ajj[rr], E[4rr + q][c] in
 // eid[rr] and, at q = 0, the bordering row's entry c in ag (left unscaled,
@@ -138,7 +157,7 @@ __device__ __forceinline__ double quarter_bcast(double v) {
 // pivot of column K and leaves as that of column K + 1 (a look-ahead on
 // a[K+1][K] and a[K+1][K+1] only); 1/sqrt(piv) is kept by lane c = K.
 template <int K>
-__device__ __forceinline__ void elim_col(const int c, const bool below, d4 &ajj, d4 &eid, double &ag,
+__device__ __forceinline__ void elim_col(const int c, d4 &ajj, d4 &eid, double &ag,
                                          double &piv, double &myinv) {
   const double inv = rsqrt_nr(piv);
   if (c == K) myinv = inv;
@@ -157,23 +176,21 @@ __device__ __forceinline__ void elim_col(const int c, const bool below, d4 &ajj,
   for (int rr = 0; rr < 4; ++rr) rowv[rr] = row_bcast<K>(ajj[rr]);
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) ajj[rr] = fma(-rowv[rr], cv2, ajj[rr]);
-  if (below) {
-    d4 rowe;
+  d4 rowe;
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) rowe[rr] = row_bcast<K>(eid[rr]);
+  for (int rr = 0; rr < 4; ++rr) rowe[rr] = row_bcast<K>(eid[rr]);
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) eid[rr] = fma(-rowe[rr], cv2, eid[rr]);
-  }
+  for (int rr = 0; rr < 4; ++rr) eid[rr] = fma(-rowe[rr], cv2, eid[rr]);
   ag = fma(-ab, cv1, ag);   // entries c <= K stay as they are (cv1 = 0)
 }
 
 // Columns K..15; false at the first pivot that is not positive (or NaN).
 template <int K>
-__device__ __forceinline__ bool elim_cols(const int c, const bool below, d4 &ajj, d4 &eid, double &ag,
+__device__ __forceinline__ bool elim_cols(const int c, d4 &ajj, d4 &eid, double &ag,
                                           double &piv, double &myinv) {
   if (!(piv > 0.0)) return false;
-  elim_col<K>(c, below, ajj, eid, ag, piv, myinv);
-  if constexpr (K + 1 < 16) return elim_cols<K + 1>(c, below, ajj, eid, ag, piv, myinv);
+  elim_col<K>(c, ajj, eid, ag, piv, myinv);
+  if constexpr (K + 1 < 16) return elim_cols<K + 1>(c, ajj, eid, ag, piv, myinv);
   return true;
 }
 
@@ -229,8 +246,7 @@ __device__ __forceinline__ void adj_rhs(const int lane, const int64_t r, const i
 #pragma unroll
   for (int I = 0; I < T; ++I) {
     double es = e[I];
-    es += __shfl_xor(es, 16, 64);
-    es += __shfl_xor(es, 32, 64);
+    es = quarter_sum(es);
     const int k = 16 * I + c;
     const bool ok = k < N;
     const double eps = ok ? U[uoff + k] - es : 0.0;
@@ -276,8 +292,7 @@ __device__ __forceinline__ void adj_rhs(const int lane, const int64_t r, const i
 #pragma unroll
   for (int I = 0; I < T; ++I) {
     double t = tacc[I];
-    t += __shfl_xor(t, 16, 64);
-    t += __shfl_xor(t, 32, 64);
+    t = quarter_sum(t);
     augv[I] = (q == 0 && 16 * I + c < N) ? t : 0.0;
   }
   wave_lds_sync();
@@ -417,16 +432,14 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     if constexpr (ADJ) {
 #pragma unroll
       for (int I = 0; I < T; ++I) {
-        vp[I] += __shfl_xor(vp[I], 16, 64);
-        vp[I] += __shfl_xor(vp[I], 32, 64);
+        vp[I] = quarter_sum(vp[I]);
         const int a = 16 * I + c;
         augv[I] = (a < p && q == 0) ? adj.sb[lo + a] - vp[I] : 0.0;   // b_a
       }
     } else {
 #pragma unroll
       for (int I = 0; I < T; ++I) {
-        vp[I] += __shfl_xor(vp[I], 16, 64);
-        vp[I] += __shfl_xor(vp[I], 32, 64);
+        vp[I] = quarter_sum(vp[I]);
         augv[I] = (16 * I + c < m && q == 0) ? vp[I] : 0.0;
       }
     }
@@ -459,14 +472,14 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     // pivot of the panel's first column (after the trailing updates)
     double piv = readlane_d(acc[tix<T>(J, J)][0], 0);
     double myinv = 0.0;
-    if (!elim_cols<0>(c, below, acc[tix<T>(J, J)], eid, augv[J], piv, myinv)) {
+    if (!elim_cols<0>(c, acc[tix<T>(J, J)], eid, augv[J], piv, myinv)) {
       if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
       return;
     }
-    if (q == 0) L.dinv[16 * J + c] = myinv;
     augv[J] *= myinv;
-    acc[tix<T>(J, J)] *= myinv;
     eid *= myinv;   // L_JJ^-T; the accumulator layout is the B operand layout
+    // L_JJ itself is not needed again: its slot keeps L_JJ^-T for step 4
+    acc[tix<T>(J, J)] = eid;
     if (below) {
       // L_IJ = A_IJ L_JJ^-T, the A operand transposed through LDS
 #pragma unroll
@@ -522,6 +535,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   }
 
   // ---- 4. back substitution L^T x = y (y = the factored bordering row) ----
+  // Panel by panel from the last: t = y_J - sum_{I>J} L_IJ^T x_I, then
+  // x_J = L_JJ^-T t, a product with the tile kept in the diagonal slot (lane
+  // (q, c) holds L_JJ^-T[4rr + q][c]; the 16 lanes of row q add up entry
+  // 4rr + q of x_J).
   double *y = L.vec;   // y then x, natural order
   if (q == 0) {
 #pragma unroll
@@ -536,25 +553,16 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) s += acc[tix<T>(I, J)][rr] * y[16 * I + 4 * rr + q];
     }
-    s += __shfl_xor(s, 16, 64);
-    s += __shfl_xor(s, 32, 64);
-    double t = y[16 * J + c] - s;        // replicated over q
-    double *tb = L.tile;                 // diagonal tile row-major: (i, j) at i*17 + j
+    s = quarter_sum(s);
+    const double t = y[16 * J + c] - s;        // replicated over q
+    double xr[4];
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) tb[(4 * rr + q) * kTileLd + c] = acc[tix<T>(J, J)][rr];
+    for (int rr = 0; rr < 4; ++rr) xr[rr] = row16_sum(acc[tix<T>(J, J)][rr] * t);
     wave_lds_sync();
-    double lrow[16];
+    if (c == 0) {
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) lrow[jj] = tb[jj * kTileLd + c];   // L_JJ(jj, c)
-    double xc = 0.0;
-#pragma unroll
-    for (int jj = 15; jj >= 0; --jj) {
-      const double xj = readlane_d(t, jj) * L.dinv[16 * J + jj];
-      if (c == jj) xc = xj;
-      if (c < jj) t -= lrow[jj] * xj;
+      for (int rr = 0; rr < 4; ++rr) y[16 * J + 4 * rr + q] = xr[rr];   // x_J overwrites y_J
     }
-    wave_lds_sync();
-    if (q == 0) y[16 * J + c] = xc;   // x_J overwrites y_J (no longer needed)
     wave_lds_sync();
   }
 
@@ -613,8 +621,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       double e = 0.0;
 #pragma unroll
       for (int j = 0; j < 4 * T; ++j) e = fma(bq[j], U[off[j] + 16 * I], e);
-      e += __shfl_xor(e, 16, 64);
-      e += __shfl_xor(e, 32, 64);
+      e = quarter_sum(e);
       if (q == 0 && 16 * I + c < N) {
         const double eps = U[uoff + 16 * I + c] - e;
         ss += eps * eps;
@@ -669,8 +676,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
       for (int I = 0; I < T; ++I) {
         double e = gacc[I];
-        e += __shfl_xor(e, 16, 64);
-        e += __shfl_xor(e, 32, 64);
+        e = quarter_sum(e);
         const int k = 16 * I + c;
         if (q == 0 && k < N) adj.e2[r * N + k] = -(e / nm1 + adj.e2[r * N + k]);
       }
@@ -717,8 +723,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       for (int I = 0; I < kMaxT; ++I) {
         if (I >= nt) break;
         double es = e[I];
-        es += __shfl_xor(es, 16, 64);
-        es += __shfl_xor(es, 32, 64);
+        es = quarter_sum(es);
         const int k = 16 * I + c;
         if (q == 0 && k < N) adj.e2[r * N + k] = -(es / nm1 + adj.ebl[k]);
       }
