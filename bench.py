@@ -49,8 +49,8 @@ def fit_flops(counts, N):
 # counters, each scaled by what the same counter reads for a plain copy of
 # known size.  Valid only for the kernel source it was taken on: a changed
 # source reports null.
-TRAFFIC = {"fit_batched_sha256": "95b36c8bbd12f25e16bc6d9089af1e48914f1b47d0241ca3299738f201f011bb",
-           "fetch_bytes": 1.7594e+09, "write_bytes": 9.1895e+08, "bytes_per_launch": 2.6783e+09,
+TRAFFIC = {"fit_batched_sha256": "087e9169be22559d313ff9b4e99362187755e26577a6343ad26fb5bbbf0d8f34",
+           "fetch_bytes": 1.7592e+09, "write_bytes": 9.1895e+08, "bytes_per_launch": 2.6782e+09,
            "fetch_scale": 1.9999, "write_scale": 1.0}
 
 
