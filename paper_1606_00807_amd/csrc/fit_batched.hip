@@ -514,20 +514,23 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
       for (int I2 = J + 1; I2 < T; ++I2) {
         const double *tb2 = L.tile + (I2 - J - 1) * 16 * kTileLd;
-        double fbk[4];
+        double fbk[4];   // negated once here rather than in every product
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) fbk[kc] = tb2[c * kTileLd + 4 * kc + q];
+        for (int kc = 0; kc < 4; ++kc) fbk[kc] = -tb2[c * kTileLd + 4 * kc + q];
 #pragma unroll
         for (int I = I2; I < T; ++I) {
           const double *tb = L.tile + (I - J - 1) * 16 * kTileLd;
           d4 a = acc[tix<T>(I, I2)];
 #pragma unroll
-          for (int kc = 0; kc < 4; ++kc) a = mfma64(-tb[c * kTileLd + 4 * kc + q], fbk[kc], a);
+          for (int kc = 0; kc < 4; ++kc) a = mfma64(tb[c * kTileLd + 4 * kc + q], fbk[kc], a);
           acc[tix<T>(I, I2)] = a;
         }
         d4 a = d4{augv[I2], 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) a = mfma64(c == 0 ? -tba[4 * kc + q] : 0.0, fbk[kc], a);
+        for (int kc = 0; kc < 4; ++kc) {
+          const double tv = tba[4 * kc + q];   // read by every lane, used at c = 0
+          a = mfma64(c == 0 ? tv : 0.0, fbk[kc], a);
+        }
         augv[I2] = a[0];
       }
       wave_lds_sync();
