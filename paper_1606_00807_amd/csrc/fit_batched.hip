@@ -194,6 +194,23 @@ __device__ __forceinline__ bool elim_cols(const int c, d4 &ajj, d4 &eid, double 
   return true;
 }
 
+// Four 16-lane sums at once: on return lanes 4u..4u+3 of each row of 16 hold
+// the row's sum of v_u.  The row mirror pairs lane i with 15 - i: the low half
+// keeps v0, v1 and the high half v2, v3, each adding its partner's.  The half
+// mirror (i with 7 - i) halves that again, leaving v_u in quad u summed over
+// four lanes; two quad exchanges finish each sum.
+__device__ __forceinline__ double row16_sum4(const double v0, const double v1, const double v2, const double v3,
+                                             const int c) {
+  const bool lo8 = c < 8;
+  const double r0 = (lo8 ? v0 : v2) + dpp_d<0x140>(lo8 ? v2 : v0);   // row_mirror
+  const double r1 = (lo8 ? v1 : v3) + dpp_d<0x140>(lo8 ? v3 : v1);
+  const bool lo4 = (c & 7) < 4;
+  double s = (lo4 ? r0 : r1) + dpp_d<0x141>(lo4 ? r1 : r0);         // row_half_mirror
+  s += dpp_d<0xB1>(s);                                                 // quad_perm [1,0,3,2]
+  s += dpp_d<0x4E>(s);                                                 // quad_perm [2,3,0,1]
+  return s;
+}
+
 // Arrays of the adjoint pass.
 struct AdjIO {
   const double *dbar;   // dL/dd per fit row
@@ -592,15 +609,17 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
         for (int I = 0; I < T; ++I) f[u][I] = U[off + 16 * I];
       }
+      double bu[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int a = 4 * (ks0 + u) + q;
-        double b = 0.0;
+        bu[u] = 0.0;
 #pragma unroll
-        for (int I = 0; I < T; ++I) b = fma(f[u][I], wv[I], b);
-        b = row16_sum(b);
-        if (c == 0 && a < p) tval[lo + a] = -b;
+        for (int I = 0; I < T; ++I) bu[u] = fma(f[u][I], wv[I], bu[u]);
       }
+      // lanes 4u..4u+3 get beta of predecessor 4(ks0 + u) + q
+      const double b = row16_sum4(bu[0], bu[1], bu[2], bu[3], c);
+      const int a = 4 * (ks0 + (c >> 2)) + q;
+      if ((c & 3) == 0 && a < p) tval[lo + a] = -b;
     }
     if (q == 0) {
 #pragma unroll
