@@ -42,13 +42,12 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxT = 5;          // largest tile count handled here (m <= 80)
 constexpr int kMaxP = 128;        // largest predecessor count handled here
-constexpr int kTileLd = 17;       // padded row stride of the transpose buffer
 
 template <int T>
 struct WaveLds {                  // wavefront-private LDS (doubles unless noted)
   int pidx[kMaxP + 8];            // global rows of the predecessors, pad row beyond p
   double vec[16 * (T + 1)];
-  double tile[T * 16 * kTileLd];
+  double tile[kMaxP + 16 * kMaxT]; // scratch: bordering row, adjoint vectors
 };
 
 __device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
@@ -332,6 +331,9 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
   // ---- 1. Gram (+ right-hand side) -----------------------------------------
+  // Tile (I, J), I > J, is kept transposed: acc[tix(I, J)] holds A_IJ^T (the
+  // operands of its products swapped), so that the factorisation below needs
+  // no transposes.
   // pidx[k] for k >= p names the all-zero pad row of U, so padded fragments
   // load zeros; the loads of step ks+1 are issued before the MFMAs of ks.
   if (KF) {
@@ -355,7 +357,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
       for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[I], fa[J], acc[tix<T>(I, J)]);
+        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
       __builtin_amdgcn_sched_barrier(0);
       const int offa = L.pidx[4 * ks + 8 + q] * ldu + c;
 #pragma unroll
@@ -364,7 +366,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
       for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fb[I], fb[J], acc[tix<T>(I, J)]);
+        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fb[J], fb[I], acc[tix<T>(I, J)]);
       __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (!ADJ) {
@@ -411,11 +413,11 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
         for (int I = 0; I < T; ++I)
 #pragma unroll
-          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I].x, f[J].x, acc[tix<T>(I, J)]);
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[J].x, f[I].x, acc[tix<T>(I, J)]);
 #pragma unroll
         for (int I = 0; I < T; ++I) {
 #pragma unroll
-          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I].y, f[J].y, acc[tix<T>(I, J)]);
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[J].y, f[I].y, acc[tix<T>(I, J)]);
           vp[I] = fma(f[I].x, uk.x, vp[I]);
           vp[I] = fma(f[I].y, uk.y, vp[I]);
         }
@@ -431,7 +433,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
         for (int I = 0; I < T; ++I) {
 #pragma unroll
-          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[I], f[J], acc[tix<T>(I, J)]);
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[J], f[I], acc[tix<T>(I, J)]);
           es = fma(bet[I], f[I], es);
         }
         es = row16_sum(es);
@@ -498,55 +500,37 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     // L_JJ itself is not needed again: its slot keeps L_JJ^-T for step 4
     acc[tix<T>(J, J)] = eid;
     if (below) {
-      // L_IJ = A_IJ L_JJ^-T, the A operand transposed through LDS
+      // L_IJ^T = L_JJ^-1 A_IJ^T: E's registers as the A operand give E^T =
+      // L_JJ^-1, and the stored A_IJ^T is the B operand of its own registers.
 #pragma unroll
       for (int I = J + 1; I < T; ++I) {
-        double *tb = L.tile + (I - J - 1) * 16 * kTileLd;
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) tb[(4 * rr + q) * kTileLd + c] = acc[tix<T>(I, J)][rr];
-      }
-      wave_lds_sync();
-#pragma unroll
-      for (int I = J + 1; I < T; ++I) {
-        const double *tb = L.tile + (I - J - 1) * 16 * kTileLd;
         d4 a = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) a = mfma64(tb[c * kTileLd + 4 * kc + q], eid[kc], a);
+        for (int kc = 0; kc < 4; ++kc) a = mfma64(eid[kc], acc[tix<T>(I, J)][kc], a);
         acc[tix<T>(I, J)] = a;
       }
-      wave_lds_sync();
-    }
-    if (J + 1 < T) {
-      // transpose the panel tiles below the diagonal into LDS (row-major, padded);
-      // the bordering row becomes row 0 of the last buffer (rows 1..15 unused)
-#pragma unroll
-      for (int I = J + 1; I < T; ++I) {
-        double *tb = L.tile + (I - J - 1) * 16 * kTileLd;
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) tb[(4 * rr + q) * kTileLd + c] = acc[tix<T>(I, J)][rr];
-      }
-      double *tba = L.tile + (T - J - 1) * 16 * kTileLd;
+      // Trailing update, kept transposed: A_{I,I2}^T -= L_{I2,J} L_{I,J}^T, the
+      // A operand from the registers of L_{I2,J}^T (negated once) and the B
+      // operand those of L_{I,J}^T.  The bordering row enters as row 0 of an A
+      // operand, through LDS.
+      double *tba = L.tile;
       if (q == 0) tba[c] = augv[J];
       wave_lds_sync();
 #pragma unroll
       for (int I2 = J + 1; I2 < T; ++I2) {
-        const double *tb2 = L.tile + (I2 - J - 1) * 16 * kTileLd;
-        double fbk[4];   // negated once here rather than in every product
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc) fbk[kc] = -tb2[c * kTileLd + 4 * kc + q];
+        const d4 ny = -acc[tix<T>(I2, J)];
 #pragma unroll
         for (int I = I2; I < T; ++I) {
-          const double *tb = L.tile + (I - J - 1) * 16 * kTileLd;
           d4 a = acc[tix<T>(I, I2)];
 #pragma unroll
-          for (int kc = 0; kc < 4; ++kc) a = mfma64(tb[c * kTileLd + 4 * kc + q], fbk[kc], a);
+          for (int kc = 0; kc < 4; ++kc) a = mfma64(ny[kc], acc[tix<T>(I, J)][kc], a);
           acc[tix<T>(I, I2)] = a;
         }
         d4 a = d4{augv[I2], 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc) {
           const double tv = tba[4 * kc + q];   // read by every lane, used at c = 0
-          a = mfma64(c == 0 ? tv : 0.0, fbk[kc], a);
+          a = mfma64(c == 0 ? tv : 0.0, ny[kc], a);
         }
         augv[I2] = a[0];
       }
@@ -556,33 +540,41 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 
   // ---- 4. back substitution L^T x = y (y = the factored bordering row) ----
   // Panel by panel from the last: t = y_J - sum_{I>J} L_IJ^T x_I, then
-  // x_J = L_JJ^-T t, a product with the tile kept in the diagonal slot (lane
-  // (q, c) holds L_JJ^-T[4rr + q][c]; the 16 lanes of row q add up entry
-  // 4rr + q of x_J).
-  double *y = L.vec;   // y then x, natural order
+  // x_J = L_JJ^-T t.  Lane (q, c) holds L_IJ^T[4rr + q][c] and
+  // L_JJ^-T[4rr + q][c] in register rr, so both products multiply by the
+  // vector's entry c and sum over the row of 16 lanes; the four sums of a row
+  // go in one exchange (row16_sum4), which leaves entry 4(c/4) + q in lane
+  // (q, c).  y (then x) stays in LDS in natural order.
+  double *y = L.vec;
   if (q == 0) {
 #pragma unroll
     for (int J = 0; J < T; ++J) y[16 * J + c] = augv[J];
   }
   wave_lds_sync();
+  const int jq = 4 * (c >> 2) + q;   // the entry this lane ends up holding
 #pragma unroll
   for (int J = T - 1; J >= 0; --J) {
-    double s = 0.0;
+    double t = y[16 * J + jq];
+    if (J + 1 < T) {
+      double sr[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int I = J + 1; I < T; ++I) {
+      for (int I = J + 1; I < T; ++I) {
+        const double xc = y[16 * I + c];
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) s += acc[tix<T>(I, J)][rr] * y[16 * I + 4 * rr + q];
+        for (int rr = 0; rr < 4; ++rr) sr[rr] = fma(acc[tix<T>(I, J)][rr], xc, sr[rr]);
+      }
+      t -= row16_sum4(sr[0], sr[1], sr[2], sr[3], c);
     }
-    s = quarter_sum(s);
-    const double t = y[16 * J + c] - s;        // replicated over q
+    wave_lds_sync();
+    if ((c & 3) == 0) y[16 * J + jq] = t;
+    wave_lds_sync();
+    const double tc = y[16 * J + c];
     double xr[4];
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) xr[rr] = row16_sum(acc[tix<T>(J, J)][rr] * t);
+    for (int rr = 0; rr < 4; ++rr) xr[rr] = acc[tix<T>(J, J)][rr] * tc;
+    const double x = row16_sum4(xr[0], xr[1], xr[2], xr[3], c);
     wave_lds_sync();
-    if (c == 0) {
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr) y[16 * J + 4 * rr + q] = xr[rr];   // x_J overwrites y_J
-    }
+    if ((c & 3) == 0) y[16 * J + jq] = x;   // x_J overwrites t
     wave_lds_sync();
   }
 
