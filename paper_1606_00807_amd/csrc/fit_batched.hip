@@ -170,16 +170,16 @@ __device__ __forceinline__ void elim_col(const int c, d4 &ajj, d4 &eid, double &
   const double colv = quarter_bcast<K & 3>(ajj[K >> 2]);
   const double cv1 = c > K ? colv * inv : 0.0;   // L[c][K]
   const double cv2 = cv1 * inv;
-  d4 rowv;
+  // Registers whose rows are all <= K are skipped: those rows of the tile
+  // are not read again (row K was read above, as the column).  E's column K
+  // is zero below row K, so E's registers whose rows all exceed K would not
+  // change.
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr) rowv[rr] = row_bcast<K>(ajj[rr]);
+  for (int rr = 0; rr < 4; ++rr)
+    if (4 * rr + 3 > K) ajj[rr] = fma(-row_bcast<K>(ajj[rr]), cv2, ajj[rr]);
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr) ajj[rr] = fma(-rowv[rr], cv2, ajj[rr]);
-  d4 rowe;
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) rowe[rr] = row_bcast<K>(eid[rr]);
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) eid[rr] = fma(-rowe[rr], cv2, eid[rr]);
+  for (int rr = 0; rr < 4; ++rr)
+    if (4 * rr <= K) eid[rr] = fma(-row_bcast<K>(eid[rr]), cv2, eid[rr]);
   ag = fma(-ab, cv1, ag);   // entries c <= K stay as they are (cv1 = 0)
 }
 
