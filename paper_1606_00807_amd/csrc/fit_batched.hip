@@ -624,17 +624,21 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     // eps_k = u_k - sum_a beta_a U[P_a][k]: lane (q, c) takes member 16I + c and
     // predecessors a = q mod 4; the four partial sums are then added across q.
     for (int a = lane; a < p; a += 64) tval[lo + a] = -y[a];
+    // one pointer per predecessor; the member tiles then differ by constant
+    // offsets (the loop over them is unrolled, N <= 16 kMaxT)
     double bq[4 * T];
-    int off[4 * T];
+    const double *up[4 * T];
 #pragma unroll
     for (int j = 0; j < 4 * T; ++j) {
       bq[j] = y[4 * j + q];
-      off[j] = L.pidx[4 * j + q] * ldu + c;
+      up[j] = U + ((int64_t)L.pidx[4 * j + q] * ldu + c);
     }
-    for (int I = 0; 16 * I < N; ++I) {
+#pragma unroll
+    for (int I = 0; I < kMaxT; ++I) {
+      if (16 * I >= N) break;
       double e = 0.0;
 #pragma unroll
-      for (int j = 0; j < 4 * T; ++j) e = fma(bq[j], U[off[j] + 16 * I], e);
+      for (int j = 0; j < 4 * T; ++j) e = fma(bq[j], up[j][16 * I], e);
       e = quarter_sum(e);
       if (q == 0 && 16 * I + c < N) {
         const double eps = U[uoff + 16 * I + c] - e;
