@@ -5,17 +5,19 @@
 //   m = N (kernel form, p >= N and lam > 0) or m = p (p-form), T = ceil(m/16).
 //   1. Gram  G = X^T X (+ mu I) with X = U_P (kernel form, reduction over the
 //      p predecessors) or X = U_P^T (p-form, reduction over the N members),
-//      accumulated by v_mfma_f64_16x16x4 into the T(T+1)/2 lower 16x16 tiles.
-//      Rows/columns m..16T-1 are padded with the identity.
+//      accumulated by v_mfma_f64_16x16x4 into the T(T+1)/2 lower 16x16 tiles
+//      (those below the diagonal kept transposed).  Rows/columns m..16T-1 are
+//      padded with the identity.
 //   2. The right-hand side v (v = u, or U_P u accumulated in the same pass) is
 //      a bordering row, so factoring [[G, v], [v^T, .]] also yields
 //      y = L^-1 v (forward substitution for free).
 //   3. Blocked right-looking Cholesky, panel width 16: inside a panel the 16
-//      columns are eliminated one at a time (column broadcast through a
-//      wavefront-private LDS buffer); the trailing tiles are then updated with
-//      v_mfma_f64_16x16x4 (operands transposed through LDS).
-//   4. Back substitution L^T x = y, blocked: off-diagonal tiles by
-//      wavefront reductions, diagonal tiles by 16 scalar steps.
+//      columns are eliminated one at a time in registers (cross-lane moves:
+//      DPP row broadcasts and permlane swaps), carrying an identity tile that
+//      ends as L_JJ^-T; the tiles below and the trailing tiles then follow by
+//      v_mfma_f64_16x16x4 with both operands straight from registers.
+//   4. Back substitution L^T x = y, blocked: x_J = L_JJ^-T (y_J - sum L_IJ^T
+//      x_I), tile-vector products summed across lanes.
 //   5. p-form: beta = x, eps = u - U_P^T beta;
 //      kernel form: w = x, beta = U_P w, eps = mu w.   d = eps^T eps/(N-1).
 //
@@ -463,15 +465,17 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       }
     }
   }
-  // ridge on the diagonal, identity on the padding
+  // ridge on the diagonal, identity on the padding: the padded rows and
+  // columns of the Gram are exactly zero, so adding 1 there gives it
+  d4 dmask;   // 1 where register rr holds a diagonal entry
 #pragma unroll
-  for (int J = 0; J < T; ++J)
+  for (int rr = 0; rr < 4; ++rr) dmask[rr] = (4 * rr + q == c) ? 1.0 : 0.0;
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
-      if (4 * rr + q == c) {
-        const int idx = 16 * J + c;
-        acc[tix<T>(J, J)][rr] = idx < m ? acc[tix<T>(J, J)][rr] + mu : 1.0;
-      }
+  for (int J = 0; J < T; ++J) {
+    const double dv = 16 * J + c < m ? mu : 1.0;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[tix<T>(J, J)][rr] = fma(dmask[rr], dv, acc[tix<T>(J, J)][rr]);
+  }
 
   // ---- 3. blocked Cholesky of the bordered matrix -------------------------
   // Per panel J: the 16 columns of the diagonal tile are eliminated one at a
