@@ -117,7 +117,10 @@ enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes,
  * Xb: dev (n x N), element type dtype, row stride ld >= N elements.
  * ridge >= 0 is added to the (N-1)-normalised Gram of every regression; with
  * ridge == 0 a regression with N - 1 or more predecessors is ENOTSPD.
- * mode: enkfmc_fit_mode.  T and D stay in the workspace.
+ * mode: enkfmc_fit_mode.  ENKFMC_FIT_BATCHED runs the plain kernels instead
+ * when N > 80, when a regression has more than 128 predecessors, or when
+ * (n + 2) * ldu reaches 2^31 (ldu = N rounded up to a multiple of 16).
+ * T and D stay in the workspace.
  * Errors: EINVAL, ESTATE (no workspace), ENOTSPD, ENONPOS_D, EHIP. */
 enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t ld, double ridge,
                          int32_t mode, void *stream);

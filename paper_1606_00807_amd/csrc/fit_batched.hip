@@ -856,10 +856,15 @@ static void launch_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows, int
                      d.status);
 }
 
+// Whether a plan fits the batched kernels: systems up to 80 (N <= 80 in the
+// kernel form) and up to 128 predecessors fit their register budget, and
+// they address U (n + 2 rows of ldu doubles) with 32-bit element offsets.
+static bool batched_fits(const enkfmc_plan *p) {
+  return p->N <= 16 * kMaxT && p->max_p <= kMaxP && (int64_t)(p->n + 2) * p->ldu < (int64_t(1) << 31);
+}
+
 hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s) {
-  // systems beyond 80 (N > 80 in the kernel form) or more than 128
-  // predecessors exceed this kernel's register budget: plain kernel instead
-  if (p->N > 16 * kMaxT || p->max_p > kMaxP) return launch_fit_plain(p, d, lam, s);
+  if (!batched_fits(p)) return launch_fit_plain(p, d, lam, s);   // the plain kernel takes any such plan
   phase_begin(p, ENKFMC_PH_FIT, s);
   const int32_t *rows = d.fit_rows;
   const int64_t *bo = p->bucket_off;   // bucket 0: p = 0, 1..5: p-form T, 6: p >= N
@@ -902,7 +907,7 @@ static void launch_adj_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows,
 // Adjoint of every regression over the fit's buckets.  hipErrorNotSupported
 // when the sizes exceed this kernel (the caller then uses the plain form).
 hipError_t launch_adj_regress_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s) {
-  if (p->N > 16 * kMaxT || p->max_p > kMaxP) return hipErrorNotSupported;
+  if (!batched_fits(p)) return hipErrorNotSupported;
   const AdjIO adj{d.dbar, d.aux3, d.aux1, d.aux2, d.red};
   const int32_t *rows = d.fit_rows;
   const int64_t *bo = p->bucket_off;
