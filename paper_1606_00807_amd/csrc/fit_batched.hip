@@ -339,12 +339,13 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   // pidx[k] for k >= p names the all-zero pad row of U, so padded fragments
   // load zeros; the loads of step ks+1 are issued before the MFMAs of ks.
   if (KF) {
-    // An even number of k-steps and no exit inside the loop body: with an exit
-    // between the two halves the compiler copied every accumulator on each
-    // trip and dropped the prefetch.  An odd count gets one step on the zero
-    // pad row, and the prefetch one step past the end also reads pad entries
+    // Pairs of k-steps and no exit inside the loop body: with an exit between
+    // the two halves the compiler copied every accumulator on each trip and
+    // dropped the prefetch.  An odd last step runs after the loop from the
+    // last prefetch; the prefetch one step past the end reads pad entries
     // (pidx holds kMaxP + 8 entries, 4 * 32 + 3 < kMaxP + 8).
-    const int kse = (((p + 3) >> 2) + 1) & ~1;
+    const int ksn = (p + 3) >> 2;   // k-steps with at least one predecessor
+    const int kse = ksn & ~1;        // done in pairs; an odd last step follows the loop
     double fa[T], fb[T];
     {
       const int off = L.pidx[q] * ldu + c;
@@ -370,6 +371,12 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
         for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fb[J], fb[I], acc[tix<T>(I, J)]);
       __builtin_amdgcn_sched_barrier(0);
+    }
+    if (ksn & 1) {   // the last prefetch holds k-step ksn - 1
+#pragma unroll
+      for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
     }
     if constexpr (!ADJ) {
 #pragma unroll
