@@ -69,6 +69,39 @@ def fit_row(U_loc: np.ndarray, i: int, P: np.ndarray, lam: float):
     return beta, d, eps
 
 
+def fit_row_svd(U_loc: np.ndarray, i: int, P: np.ndarray, lam: float):
+    """eq. (1) for local row i by the singular value decomposition of the
+    regression's design matrix, the route Section 5 proposes for accelerators.
+
+    With A = U_P^T (N x p) = W diag(sigma) V^T (thin SVD) and mu = lam (N-1),
+    the ridge solution of  min |u - A beta|^2 + mu |beta|^2  is
+        beta = V diag(sigma / (sigma^2 + mu)) W^T u,
+    the same beta as the normal equations of R6 (G = A^T A/(N-1) + lam I,
+    c = A^T u/(N-1)).  Readings as in fit_row: lam = 0 with p >= N - 1 is
+    ENOTSPD (no pseudo-inverse); D from the residual vector (R7).
+
+    Returns (beta, d, eps).
+    """
+    N = U_loc.shape[1]
+    u = U_loc[i]
+    if P.size == 0:
+        return fit_row(U_loc, i, P, lam)
+    if lam == 0.0 and P.size >= N - 1:
+        raise OracleError("ENOTSPD", f"local row {i}: {P.size} predecessors need lam > 0 with N = {N}")
+    A = U_loc[P].T
+    W, sig, Vt = np.linalg.svd(A, full_matrices=False)
+    mu = lam * (N - 1)
+    den = sig * sig + mu
+    if not np.all(den > 0.0):
+        raise OracleError("ENOTSPD", f"design matrix of local row {i} is rank deficient without a ridge")
+    beta = Vt.T @ ((sig / den) * (W.T @ u))
+    eps = u - A @ beta
+    d = float(eps @ eps) / (N - 1)
+    if not d > 0.0:
+        raise OracleError("ENONPOS_D", f"residual variance of local row {i} is not positive")
+    return beta, d, eps
+
+
 class Factors:
     """T (strictly lower part, CSR values = -beta) and D of one sub-domain."""
 
@@ -92,8 +125,11 @@ class Factors:
         return T.T @ (T / self.d[:, None])
 
 
-def fit_subdomain(U: np.ndarray, pat: Pattern, lam: float, rows=None) -> Factors:
-    """Fit every local row (or the listed ones) of one sub-domain (Alg. 3, first step)."""
+def fit_subdomain(U: np.ndarray, pat: Pattern, lam: float, rows=None, method: str = "cholesky") -> Factors:
+    """Fit every local row (or the listed ones) of one sub-domain (Alg. 3,
+    first step), by the normal equations (method "cholesky", R6) or by the
+    SVD of Section 5 (method "svd")."""
+    row_fit = fit_row_svd if method == "svd" else fit_row
     U_loc = U[pat.loc2glob]
     n = pat.n_sd
     tval = np.zeros(pat.col_idx.shape[0])
@@ -102,6 +138,6 @@ def fit_subdomain(U: np.ndarray, pat: Pattern, lam: float, rows=None) -> Factors
     todo = range(n) if rows is None else rows
     for i in todo:
         lo, hi = pat.row_ptr[i], pat.row_ptr[i + 1]
-        beta, d[i], eps[i] = fit_row(U_loc, i, pat.col_idx[lo:hi], lam)
+        beta, d[i], eps[i] = row_fit(U_loc, i, pat.col_idx[lo:hi], lam)
         tval[lo:hi] = -beta
     return Factors(pat, tval, d, eps)

@@ -287,3 +287,89 @@ def test_subdomain_index_out_of_range_is_an_error():
     for k in (-1, 6, 100):
         with pytest.raises(OracleError):
             G.box(geo, k)
+
+
+# --- the SVD route of Section 5 (fit_row_svd) ------------------------------
+
+def _centred_orthogonal_rows(p, N, rng):
+    """p rows of length N, orthogonal to each other and to the all-ones vector
+    (anomaly-like), with distinct norms; and a vector orthogonal to all of them."""
+    M = rng.standard_normal((N, p + 1))
+    M -= M.mean(axis=0)                        # columns orthogonal to 1
+    Q, _ = np.linalg.qr(M)                     # N x (p+1), orthonormal, still orthogonal to 1
+    scales = np.linspace(0.5, 3.0, p)
+    return (Q[:, :p] * scales).T, Q[:, p]
+
+
+@pytest.mark.parametrize("lam", [0.0, 1e-3, 0.7])
+def test_svd_regression_orthogonal_design_closed_form(lam):
+    """With mutually orthogonal predecessor anomalies the ridge coefficients
+    decouple: beta_a = (u . U_a) / (|U_a|^2 + lam (N-1)) (hand-derived)."""
+    rng = np.random.default_rng(21)
+    N, p = 24, 7
+    UP, _ = _centred_orthogonal_rows(p, N, rng)
+    u = rng.standard_normal(N)
+    u -= u.mean()
+    U_loc = np.vstack([UP, u])
+    beta, d, eps = F.fit_row_svd(U_loc, p, np.arange(p), lam)
+    want = (UP @ u) / (np.sum(UP * UP, axis=1) + lam * (N - 1))
+    np.testing.assert_allclose(beta, want, rtol=1e-12, atol=1e-14)
+    res = u - UP.T @ want
+    assert abs(d - res @ res / (N - 1)) <= 1e-12 * d
+
+
+def test_svd_regression_recovers_planted_coefficients():
+    """lam = 0, p < N - 1: u = U_P^T beta* + e with e orthogonal to the rows of
+    U_P gives back beta* exactly and d = |e|^2/(N-1)."""
+    rng = np.random.default_rng(22)
+    N, p = 30, 11
+    UP = rng.standard_normal((p, N))
+    UP -= UP.mean(axis=1, keepdims=True)
+    beta_star = rng.standard_normal(p)
+    e = rng.standard_normal(N)
+    e -= e.mean()
+    e -= UP.T @ np.linalg.solve(UP @ UP.T, UP @ e)   # project out the row space of U_P
+    u = UP.T @ beta_star + e
+    U_loc = np.vstack([UP, u])
+    beta, d, _ = F.fit_row_svd(U_loc, p, np.arange(p), 0.0)
+    np.testing.assert_allclose(beta, beta_star, rtol=1e-10, atol=1e-12)
+    assert abs(d - e @ e / (N - 1)) <= 1e-10 * (e @ e / (N - 1))
+
+
+@pytest.mark.parametrize("lam", [0.0, 1e-3, 0.5])
+def test_svd_regression_equals_normal_equations(lam):
+    """The SVD route and the Cholesky of the ridge normal equations (R6) are
+    different algorithms for the same beta and d: p < N and (lam > 0) p >= N."""
+    for N, r_h, cfg in [(30, 1, 107), (12, 2, 108)]:
+        if lam == 0.0 and N == 12:
+            continue   # p >= N - 1 rows need a ridge (R6)
+        p = synth.make_small(nx=11, ny=9, nlev=(3,), N=N, r_h=r_h, r_v=1, sdx=1, sdy=1, obs_frac=0.0,
+                             config=cfg)
+        _, U = F.anomalies(p.Xb)
+        pat = G.subdomain_pattern(p.geometry, 0, p.obs_idx)
+        fc = F.fit_subdomain(U, pat, lam)
+        fs = F.fit_subdomain(U, pat, lam, method="svd")
+        counts = np.diff(pat.row_ptr)
+        assert counts.max() >= N or N == 30
+        np.testing.assert_allclose(fs.tval, fc.tval, rtol=1e-8, atol=1e-9 * np.max(np.abs(fc.tval)))
+        np.testing.assert_allclose(fs.d, fc.d, rtol=1e-9)
+
+
+def test_svd_regression_large_ridge_limit():
+    """lam -> infinity: beta -> U_P u / (lam (N-1)) (first order in 1/lam)."""
+    rng = np.random.default_rng(23)
+    N, p = 20, 9
+    UP = rng.standard_normal((p, N))
+    u = rng.standard_normal(N)
+    lam = 1e8
+    beta, _, _ = F.fit_row_svd(np.vstack([UP, u]), p, np.arange(p), lam)
+    np.testing.assert_allclose(beta, UP @ u / (lam * (N - 1)), rtol=1e-6)
+
+
+def test_svd_regression_without_ridge_refuses_p_at_least_n_minus_1():
+    rng = np.random.default_rng(24)
+    N = 6
+    U_loc = rng.standard_normal((8, N))
+    with pytest.raises(OracleError) as e:
+        F.fit_row_svd(U_loc, 7, np.arange(5), 0.0)
+    assert e.value.code == "ENOTSPD"
