@@ -174,6 +174,27 @@ enkfmc_status enkfmc_perturb_observations(enkfmc_plan *p, const double *y, const
 enkfmc_status enkfmc_analysis_sq_error(enkfmc_plan *p, const void *Xa, int32_t dtype, int64_t ld,
                                        const double *x_ref, double *err, void *stream);
 
+/* The same squared error as enkfmc_analysis_sq_error, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): it needs no plan and no workspace, and
+ * calls no allocating routine.  Same arguments and arithmetic (the same
+ * kernels, so the same bits), with n (components) and N (members) given
+ * directly.  Its scratch, the 256 partial sums of the first reduction level
+ * (2 KiB), is a static device array that every GPU the library runs on holds
+ * until the process ends; it does not grow with n.  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (other streams, other
+ * threads) race and must not be issued.  The call only enqueues its two
+ * kernels on `stream` and returns without waiting; err is valid once the
+ * stream has reached that point.
+ * Limits: n <= ENKFMC_SQ_ERROR_NOALLOC_MAX_N, N <= ENKFMC_SQ_ERROR_NOALLOC_MAX_MEMBERS
+ * (larger sizes return EUNSUPPORTED).
+ * Errors: EINVAL (NULL pointer, bad dtype, n < 0, N < 1, ld < N),
+ * EUNSUPPORTED, EHIP (launch failure or scratch lookup on this device). */
+#define ENKFMC_SQ_ERROR_NOALLOC_MAX_N ((int64_t)2147483647)
+#define ENKFMC_SQ_ERROR_NOALLOC_MAX_MEMBERS 65536
+enkfmc_status enkfmc_analysis_sq_error_noalloc(int64_t n, int32_t N, const void *Xa, int32_t dtype, int64_t ld,
+                                               const double *x_ref, double *err, void *stream);
+
 /* Parity exports of sub-domain k (host copies, local numbering of Section 3).
  * Sizes first, then the arrays (any pointer may be NULL to skip it):
  *  loc2glob[n_sd]   global component of each local row

@@ -57,6 +57,8 @@ SIGNATURES = {
     "enkfmc_perturb_observations": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_uint64, c_void_p,
                                               c_void_p]),
     "enkfmc_analysis_sq_error": (c_int32, [c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_void_p]),
+    "enkfmc_analysis_sq_error_noalloc": (c_int32, [c_int64, c_int32, c_void_p, c_int32, c_int64, c_void_p,
+                                                   c_void_p, c_void_p]),
     "enkfmc_get_pattern_sizes": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_int64),
                                            POINTER(c_int64)]),
     "enkfmc_get_pattern": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_uint8), POINTER(c_int64),

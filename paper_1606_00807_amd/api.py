@@ -18,6 +18,27 @@ def _ptr(a: np.ndarray, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
+def analysis_sq_error_noalloc(Xa, x_ref, err=None):
+    """sum_g (mean_k X_a[g, k] - x_ref[g])^2 through the allocation-free entry
+    point (no plan, no workspace; the library's static scratch).  Xa (n, N)
+    float32/float64 CUDA with unit member stride, x_ref (n,) float64 CUDA
+    contiguous; err: a (1,) float64 CUDA tensor to write (allocated here when
+    None).  The call only enqueues its kernels on the current stream."""
+    import torch
+    lib = _lib.load()
+    p, dt, ld = Plan._xb_args(Xa)
+    n, N = int(Xa.shape[0]), int(Xa.shape[1])
+    if (x_ref.dtype != torch.float64 or not x_ref.is_cuda or not x_ref.is_contiguous()
+            or tuple(x_ref.shape) != (n,)):
+        raise ValueError("x_ref must be a contiguous float64 CUDA tensor of n elements")
+    if err is None:
+        err = torch.empty((1,), dtype=torch.float64, device=Xa.device)
+    check(lib.enkfmc_analysis_sq_error_noalloc(n, N, p, dt, ld, ctypes.c_void_p(x_ref.data_ptr()),
+                                               ctypes.c_void_p(err.data_ptr()),
+                                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return err
+
+
 class Plan:
     """Decomposition of one geometry (Section 3) plus its device workspace.
 

@@ -244,6 +244,23 @@ enkfmc_status enkfmc_analysis_sq_error(enkfmc_plan *p, const void *Xa, int32_t d
   return finish(p, s, "analysis_sq_error");
 }
 
+enkfmc_status enkfmc_analysis_sq_error_noalloc(int64_t n, int32_t N, const void *Xa, int32_t dtype, int64_t ld,
+                                               const double *x_ref, double *err, void *stream) {
+  if (!Xa || !x_ref || !err) return fail(ENKFMC_EINVAL, "analysis_sq_error_noalloc: NULL argument");
+  if (dtype != ENKFMC_F32 && dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "analysis_sq_error_noalloc: bad dtype");
+  if (n < 0 || N < 1 || ld < N) return fail(ENKFMC_EINVAL, "analysis_sq_error_noalloc: need n >= 0, N >= 1, ld >= N");
+  if (n > ENKFMC_SQ_ERROR_NOALLOC_MAX_N || N > ENKFMC_SQ_ERROR_NOALLOC_MAX_MEMBERS)
+    return fail(ENKFMC_EUNSUPPORTED, "analysis_sq_error_noalloc: n = " + std::to_string(n) + ", N = " +
+                                         std::to_string(N) + " exceed its limits (n <= " +
+                                         std::to_string((long long)ENKFMC_SQ_ERROR_NOALLOC_MAX_N) + ", N <= " +
+                                         std::to_string(ENKFMC_SQ_ERROR_NOALLOC_MAX_MEMBERS) + ")");
+  double *part = nullptr;
+  HIPCHK(sq_error_scratch(&part), "analysis_sq_error_noalloc: scratch lookup");
+  HIPCHK(launch_sq_error(Xa, dtype, ld, n, N, x_ref, part, err, (hipStream_t)stream),
+         "analysis_sq_error_noalloc: launch");
+  return ENKFMC_OK;
+}
+
 enkfmc_status enkfmc_get_pattern_sizes(const enkfmc_plan *p, int32_t k, int64_t *n_sd, int64_t *nnz_sd,
                                        int64_t *m_sd) {
   if (!p || k < 0 || k >= (int32_t)p->subs.size()) return fail(ENKFMC_EINVAL, "get_pattern_sizes: bad sub-domain");

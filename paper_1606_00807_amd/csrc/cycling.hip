@@ -1,9 +1,18 @@
 // Steps of the assimilation cycle around the analysis (Alg. 1): the perturbed
 // observations of one assimilation time, and the squared error of the
 // analysis mean that the RMSE of eq. (18) sums over assimilation times.
+#include <mutex>
+
 #include "device.h"
 
 namespace enkfmc {
+
+// Scratch of the allocation-free squared error: the partial sums of its first
+// reduction level.  Each GPU holds its own copy until the process ends.  Host
+// code never passes this name to a kernel (on the host it is a stand-in, not a
+// device address); it uses the address that sq_error_scratch looked up.
+static __device__ __align__(256) double scratch[kSqErrorParts];
+
 namespace {
 
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
@@ -106,6 +115,27 @@ hipError_t launch_perturb(const double *y, const double *r_diag, int64_t m, int 
   hipLaunchKernelGGL(k_perturb, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, y, r_diag, m, N, seed,
                      cycle, Ys);
   return hipGetLastError();
+}
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// (with that device current) and kept for later calls.
+hipError_t sq_error_scratch(double **out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = (double *)ptr;
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_sq_error(const void *Xa, int32_t dtype, int64_t ld, int64_t n, int N, const double *xref,

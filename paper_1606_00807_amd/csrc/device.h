@@ -209,5 +209,8 @@ hipError_t launch_perturb(const double *y, const double *r_diag, int64_t m, int 
 constexpr int kSqErrorParts = 256;
 hipError_t launch_sq_error(const void *Xa, int32_t dtype, int64_t ld, int64_t n, int N, const double *xref,
                            double *part, double *out, hipStream_t s);
+// Device address of the current GPU's static scratch for those partials
+// (kSqErrorParts doubles), looked up once per device.
+hipError_t sq_error_scratch(double **out);
 
 }  // namespace enkfmc
