@@ -31,7 +31,8 @@
  *  - A stream argument is a hipStream_t passed as void* (NULL: null stream).
  *    Every device call is ordered on that stream and ends with one small
  *    device-to-host read of a status word, so it returns only after its work
- *    has finished.
+ *    has finished -- unless the plan is in asynchronous mode
+ *    (enkfmc_set_async), where calls only enqueue their kernels.
  *  - No entry point throws.  On failure a negative status is returned and
  *    enkfmc_last_error() describes it (per calling thread).
  *  - A plan is not re-entrant: calls on one plan must not overlap.  Distinct
@@ -64,7 +65,9 @@ typedef enum { ENKFMC_F32 = 0, ENKFMC_F64 = 1 } enkfmc_dtype;
 /* How enkfmc_fit computes the regressions (same result within rounding). */
 typedef enum {
   ENKFMC_FIT_PLAIN = 0,   /* one workgroup per regression, FP64 vector arithmetic */
-  ENKFMC_FIT_BATCHED = 1  /* one wavefront per regression, FP64 MFMA Gram, register Cholesky */
+  ENKFMC_FIT_BATCHED = 1, /* one wavefront per regression, FP64 MFMA Gram, register Cholesky */
+  ENKFMC_FIT_SVD = 2      /* one workgroup per regression: SVD of its design matrix by
+                             one-sided Jacobi (the route of Section 5), FP64 */
 } enkfmc_fit_mode;
 
 /* How enkfmc_analyze solves the local systems (same result within rounding). */
@@ -97,6 +100,8 @@ typedef struct {
   int32_t max_block_obs;   /* most observations in one block                         */
   int32_t reserved;
   size_t workspace_bytes;  /* device workspace enkfmc_plan_set_workspace needs       */
+  int64_t fit_rows_wave;   /* rows ENKFMC_FIT_BATCHED fits with one-wavefront kernels */
+  int64_t fit_rows_plain;  /* rows ENKFMC_FIT_BATCHED hands to the plain kernel       */
 } enkfmc_plan_info;
 
 /* Build the decomposition of Section 3 (host only, no device work).
@@ -117,11 +122,21 @@ enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes,
  * Xb: dev (n x N), element type dtype, row stride ld >= N elements.
  * ridge >= 0 is added to the (N-1)-normalised Gram of every regression; with
  * ridge == 0 a regression with N - 1 or more predecessors is ENOTSPD.
- * mode: enkfmc_fit_mode.  ENKFMC_FIT_BATCHED runs the plain kernels instead
- * when N > 80, when a regression has more than 128 predecessors, or when
- * (n + 2) * ldu reaches 2^31 (ldu = N rounded up to a multiple of 16).
+ * mode: enkfmc_fit_mode.  ENKFMC_FIT_BATCHED fits every regression with a
+ * one-wavefront kernel when N <= 128 and it has at most 192 predecessors;
+ * the other regressions (all of them when (n + 2) * ldu reaches 2^31, ldu =
+ * N rounded up to a multiple of 16) go to the plain kernel, which the
+ * counts fit_rows_wave / fit_rows_plain of enkfmc_plan_info report.
  * T and D stay in the workspace.
- * Errors: EINVAL, ESTATE (no workspace), ENOTSPD, ENONPOS_D, EHIP. */
+ * ENKFMC_FIT_SVD computes beta = V diag(sigma/(sigma^2 + mu)) W^T u from the
+ * SVD U_P^T = W diag(sigma) V^T (mu = ridge (N - 1)), the same coefficients
+ * within rounding; it keeps each regression's design matrix in LDS, so it
+ * needs p N + p^2 (p < N) and N p (p >= N) doubles to fit in 160 KiB.
+ * Errors: EINVAL, ESTATE (no workspace), ENOTSPD, ENONPOS_D, EHIP,
+ * ENOCONV (ENKFMC_FIT_SVD: a regression's Jacobi sweeps did not converge in
+ * 40 sweeps), EUNSUPPORTED (the plain kernel's N x N Gram does not fit in
+ * LDS: N > 141, in ENKFMC_FIT_PLAIN or for rows of the plain bucket; or the
+ * design matrices of ENKFMC_FIT_SVD do not). */
 enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t ld, double ridge,
                          int32_t mode, void *stream);
 
@@ -174,6 +189,12 @@ enkfmc_status enkfmc_perturb_observations(enkfmc_plan *p, const double *y, const
 enkfmc_status enkfmc_analysis_sq_error(enkfmc_plan *p, const void *Xa, int32_t dtype, int64_t ld,
                                        const double *x_ref, double *err, void *stream);
 
+/* RMSE of the analysis mean over M assimilation times, eq. (18) as printed
+ * (no 1/n): out[0] = sqrt((1/M) sum_t sq_err[t]), with sq_err (dev, M >= 1
+ * float64) the values of enkfmc_analysis_sq_error.  One kernel, fixed-order
+ * sum; only enqueued on `stream`.  Errors: EINVAL, EHIP. */
+enkfmc_status enkfmc_rmse(const double *sq_err, int64_t M, double *out, void *stream);
+
 /* The same squared error as enkfmc_analysis_sq_error, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): it needs no plan and no workspace, and
@@ -216,10 +237,31 @@ enkfmc_status enkfmc_get_factors(enkfmc_plan *p, int32_t k, double *tval, double
  * halo rows included. */
 enkfmc_status enkfmc_get_increment(enkfmc_plan *p, int32_t k, double *Z, void *stream);
 
+/* Asynchronous mode of a plan (enable != 0), for running many plans
+ * concurrently and for capturing calls into a HIP graph: enkfmc_fit,
+ * enkfmc_analyze and enkfmc_analyze_backward then only enqueue their kernels
+ * (no memset, no device-to-host read, no synchronisation) and return
+ * ENKFMC_OK unless an argument or launch fails.  Device-side failures
+ * (ENOTSPD, ENONPOS_D, ENOCONV) accumulate in the plan's status word, first
+ * failure kept, until enkfmc_check_status reads it: it synchronises `stream`,
+ * returns the recorded status (with enkfmc_last_error naming the row or
+ * block) and clears the word.  Phase timing is off in this mode.  The state
+ * checks of the calls (fit before analyze, same inputs before the reverse
+ * pass) still apply, to the enqueued order. */
+enkfmc_status enkfmc_set_async(enkfmc_plan *p, int32_t enable);
+enkfmc_status enkfmc_check_status(enkfmc_plan *p, void *stream);
+
+/* Device timestamp for latency measurements: one kernel writes the device's
+ * constant-rate wall clock (ticks of enkfmc_wall_clock_hz) to dev (a device
+ * uint64) when the stream reaches it.  Capturable into a HIP graph. */
+enkfmc_status enkfmc_timestamp(uint64_t *dev, void *stream);
+enkfmc_status enkfmc_wall_clock_hz(int64_t *hz);
+
 /* Per-phase kernel timing (HIP events recorded on the call's stream around
  * each kernel).  enable != 0 turns it on for later calls; enkfmc_get_timing
- * returns the duration in ms of phase `phase` in the most recent call that
- * ran it (0 if none).  Phases: */
+ * returns the duration in ms of phase `phase` in the most recent timed call
+ * (0 if that call did not run it: every timed call clears the others).
+ * Phases: */
 enum {
   ENKFMC_PH_ANOMALY = 0,   /* mean and anomalies, eq. (5)                          */
   ENKFMC_PH_FIT = 1,       /* regressions, eq. (1)                                 */
@@ -237,7 +279,8 @@ enum {
   ENKFMC_PH_ADJ_FACTOR = 13, /* adjoint: Dbar, betabar (within BACKWARD)           */
   ENKFMC_PH_ADJ_REGRESS = 14, /* adjoint of the regressions (within BACKWARD)      */
   ENKFMC_PH_ADJ_GATHER = 15, /* adjoint: halo gathers, dlog r, dlam (within BACKWARD) */
-  ENKFMC_PH_COUNT = 16
+  ENKFMC_PH_FIT_FALLBACK = 16, /* batched fit: rows of the plain bucket alone, within FIT */
+  ENKFMC_PH_COUNT = 17
 };
 enkfmc_status enkfmc_set_timing(enkfmc_plan *p, int32_t enable);
 enkfmc_status enkfmc_get_timing(const enkfmc_plan *p, int32_t phase, double *ms);

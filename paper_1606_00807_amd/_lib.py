@@ -17,11 +17,11 @@ ENKFMC_OK = 0
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "ENONPOS_D", -4: "ENOCONV", -5: "EHIP", -6: "ENOMEM",
           -7: "ESTATE", -8: "EUNSUPPORTED"}
 F32, F64 = 0, 1
-FIT_PLAIN, FIT_BATCHED = 0, 1
+FIT_PLAIN, FIT_BATCHED, FIT_SVD = 0, 1, 2
 SOLVE_DUAL = 0
 PHASES = ["anomaly", "fit", "dual_F", "dual_S", "dual_chol", "dual_Q", "dual_G", "sweep", "mapback", "backward",
           "tiles", "fit_kform",
-          "adj_solve", "adj_factor", "adj_regress", "adj_gather"]
+          "adj_solve", "adj_factor", "adj_regress", "adj_gather", "fit_fallback"]
 
 
 class Geometry(ctypes.Structure):
@@ -33,7 +33,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n", c_int64), ("N", c_int64), ("m", c_int64), ("n_subdomains", c_int64), ("n_blocks", c_int64),
                 ("n_fit", c_int64), ("nnz", c_int64), ("m_local", c_int64), ("max_p", c_int32),
                 ("max_block_rows", c_int32), ("max_block_obs", c_int32), ("reserved", c_int32),
-                ("workspace_bytes", c_size_t)]
+                ("workspace_bytes", c_size_t), ("fit_rows_wave", c_int64), ("fit_rows_plain", c_int64)]
 
 
 class EnkfmcError(RuntimeError):
@@ -59,6 +59,7 @@ SIGNATURES = {
     "enkfmc_analysis_sq_error": (c_int32, [c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_void_p]),
     "enkfmc_analysis_sq_error_noalloc": (c_int32, [c_int64, c_int32, c_void_p, c_int32, c_int64, c_void_p,
                                                    c_void_p, c_void_p]),
+    "enkfmc_rmse": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p]),
     "enkfmc_get_pattern_sizes": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_int64),
                                            POINTER(c_int64)]),
     "enkfmc_get_pattern": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_uint8), POINTER(c_int64),
@@ -66,6 +67,10 @@ SIGNATURES = {
     "enkfmc_get_factors": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), c_void_p]),
     "enkfmc_get_increment": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_void_p]),
     "enkfmc_set_timing": (c_int32, [c_void_p, c_int32]),
+    "enkfmc_set_async": (c_int32, [c_void_p, c_int32]),
+    "enkfmc_check_status": (c_int32, [c_void_p, c_void_p]),
+    "enkfmc_timestamp": (c_int32, [c_void_p, c_void_p]),
+    "enkfmc_wall_clock_hz": (c_int32, [POINTER(c_int64)]),
     "enkfmc_get_timing": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "enkfmc_status_string": (c_char_p, [c_int32]),
     "enkfmc_last_error": (c_char_p, []),

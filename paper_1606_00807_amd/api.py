@@ -9,9 +9,9 @@ from typing import Dict, Optional, Tuple
 import numpy as np
 
 from . import _lib
-from ._lib import EnkfmcError, F32, F64, FIT_BATCHED, FIT_PLAIN, SOLVE_DUAL, check  # noqa: F401
+from ._lib import EnkfmcError, F32, F64, FIT_BATCHED, FIT_PLAIN, FIT_SVD, SOLVE_DUAL, check  # noqa: F401
 
-_MODES = {"plain": FIT_PLAIN, "batched": FIT_BATCHED}
+_MODES = {"plain": FIT_PLAIN, "batched": FIT_BATCHED, "svd": FIT_SVD}
 
 
 def _ptr(a: np.ndarray, ctype):
@@ -37,6 +37,23 @@ def analysis_sq_error_noalloc(Xa, x_ref, err=None):
                                                ctypes.c_void_p(err.data_ptr()),
                                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
     return err
+
+
+def timestamp(slot) -> None:
+    """Enqueue a write of the device wall clock into `slot` (a one-element
+    int64 CUDA tensor or a view of one) on the current stream."""
+    import torch
+    if slot.dtype != torch.int64 or not slot.is_cuda or slot.numel() != 1:
+        raise ValueError("slot must be a one-element int64 CUDA tensor")
+    check(_lib.load().enkfmc_timestamp(ctypes.c_void_p(slot.data_ptr()),
+                                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+
+def wall_clock_hz() -> int:
+    """Rate of the device wall clock that timestamp() reads."""
+    hz = ctypes.c_int64()
+    check(_lib.load().enkfmc_wall_clock_hz(ctypes.byref(hz)))
+    return int(hz.value)
 
 
 class Plan:
@@ -110,6 +127,17 @@ class Plan:
 
     def set_timing(self, enable: bool = True) -> None:
         check(self.lib.enkfmc_set_timing(self._h, 1 if enable else 0))
+
+    def set_async(self, enable: bool = True) -> None:
+        """Calls only enqueue their kernels (no status read, no memset), so
+        that several plans run concurrently and calls can be captured into a
+        HIP graph; check_status() reads the accumulated device status."""
+        check(self.lib.enkfmc_set_async(self._h, 1 if enable else 0))
+
+    def check_status(self) -> None:
+        """Synchronise the current stream and raise the first device-side
+        failure recorded since the last check (asynchronous mode)."""
+        check(self.lib.enkfmc_check_status(self._h, self._stream()))
 
     def timing(self) -> Dict[str, float]:
         out = {}

@@ -25,18 +25,22 @@ class EnkfmcAnalysis(torch.autograd.Function):
         Xa = plan.analyze(Xd, Y, r)
         ctx.plan = plan
         ctx.token = plan.analysis_token
-        ctx.inputs = (plan._analysis_inputs[0], r, lam, mode)
-        ctx.save_for_backward(Xd)
+        ctx.inputs = (r, lam, mode)
+        # Y (the device copy the analysis read, possibly the caller's own
+        # tensor) goes through save_for_backward, so that overwriting it in
+        # place before the reverse pass raises instead of giving wrong
+        # gradients
+        ctx.save_for_backward(Xd, plan._analysis_inputs[0])
         ctx.meta = (Xb.dtype, log_r.dtype, ridge.dtype if isinstance(ridge, torch.Tensor) else None,
                     ridge.shape if isinstance(ridge, torch.Tensor) else None)
         return Xa
 
     @staticmethod
     def backward(ctx, gXa):
-        (Xd,) = ctx.saved_tensors
+        Xd, Yd = ctx.saved_tensors
         plan = ctx.plan
         if plan.analysis_token != ctx.token:
-            Yd, r, lam, mode = ctx.inputs
+            r, lam, mode = ctx.inputs
             plan.fit(Xd, lam, mode=mode)
             plan.analyze(Xd, Yd, r)
         dXb, dlogR, dridge = plan.backward(Xd, gXa.detach())

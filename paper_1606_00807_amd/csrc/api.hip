@@ -25,8 +25,42 @@ static enkfmc_status hip_fail(hipError_t e, const char *where) {
     if (e_ != hipSuccess) return hip_fail(e_, where); \
   } while (0)
 
+// The status word is cleared by a kernel rather than a memset, so that a call
+// captured into a HIP graph records no memset node.
+__global__ void k_status_clear(int32_t *status) {
+  if (threadIdx.x < 16) status[threadIdx.x] = 0;
+}
+
+// The device's constant-rate wall clock, written by one thread.
+__global__ void k_timestamp(uint64_t *out) {
+  if (threadIdx.x == 0) *out = wall_clock64();
+}
+
+static hipError_t clear_status(enkfmc_plan *p, hipStream_t s) {
+  hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(64), 0, s, (int32_t *)(p->ws + p->lay.status));
+  return hipGetLastError();
+}
+
+static enkfmc_status decode_status(const int32_t st[2], const char *what) {
+  if (st[0] == 0) return ENKFMC_OK;
+  std::string where;
+  if (st[1] >= 0) where = " (fit row " + std::to_string(st[1]) + ")";
+  else where = " (block " + std::to_string(-1 - st[1]) + ")";
+  const char *why = st[0] == ENKFMC_ENOTSPD ? "matrix not positive definite"
+                    : st[0] == ENKFMC_ENONPOS_D ? "residual variance not positive"
+                    : st[0] == ENKFMC_ENOCONV   ? "iteration did not converge"
+                                                : "device error";
+  return fail((enkfmc_status)st[0], std::string(what) + ": " + why + where);
+}
+
 // Read back the device status word (the one device->host read of each call).
+// In asynchronous mode the call returns at once: errors stay in the status
+// word until enkfmc_check_status reads it.
 static enkfmc_status finish(enkfmc_plan *p, hipStream_t s, const char *what) {
+  if (p->async) {
+    HIPCHK(hipGetLastError(), what);
+    return ENKFMC_OK;
+  }
   int32_t st[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(st, p->ws + p->lay.status, sizeof(st), hipMemcpyDeviceToHost, s), what);
   HIPCHK(hipStreamSynchronize(s), what);
@@ -39,16 +73,7 @@ static enkfmc_status finish(enkfmc_plan *p, hipStream_t s, const char *what) {
     }
     p->recorded = 0;
   }
-  if (st[0] != 0) {
-    std::string where;
-    if (st[1] >= 0) where = " (fit row " + std::to_string(st[1]) + ")";
-    else where = " (block " + std::to_string(-1 - st[1]) + ")";
-    const char *why = st[0] == ENKFMC_ENOTSPD ? "matrix not positive definite"
-                      : st[0] == ENKFMC_ENONPOS_D ? "residual variance not positive"
-                                                  : "device error";
-    return fail((enkfmc_status)st[0], std::string(what) + ": " + why + where);
-  }
-  return ENKFMC_OK;
+  return decode_status(st, what);
 }
 
 static enkfmc_status begin(enkfmc_plan *p, hipStream_t s, const char *what) {
@@ -56,7 +81,11 @@ static enkfmc_status begin(enkfmc_plan *p, hipStream_t s, const char *what) {
   int dev = -1;
   HIPCHK(hipGetDevice(&dev), what);
   if (dev != p->device) return fail(ENKFMC_ESTATE, std::string(what) + ": current device differs from the workspace's");
-  HIPCHK(hipMemsetAsync(p->ws + p->lay.status, 0, 64, s), what);
+  if (!p->async) HIPCHK(clear_status(p, s), what);
+  if (p->timing) {   // a timed call reports only the phases it runs
+    for (double &ms : p->phase_ms) ms = 0.0;
+    p->recorded = 0;
+  }
   return ENKFMC_OK;
 }
 
@@ -105,6 +134,8 @@ enkfmc_status enkfmc_plan_get_info(const enkfmc_plan *p, enkfmc_plan_info *info)
   info->max_block_obs = p->max_bm;
   info->reserved = 0;
   info->workspace_bytes = p->lay.total;
+  info->fit_rows_plain = p->bucket_off[kBucketPlain + 1] - p->bucket_off[kBucketPlain];
+  info->fit_rows_wave = p->n_fit - info->fit_rows_plain;
   return ENKFMC_OK;
 }
 
@@ -146,6 +177,7 @@ enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes,
   HIPCHK(put(p, L.ct_row, p->ct_row, s), "set_workspace");
   HIPCHK(put(p, L.ct_slot, p->ct_slot, s), "set_workspace");
   HIPCHK(put(p, L.tile_eoff, p->tile_eoff, s), "set_workspace");
+  HIPCHK(clear_status(p, s), "set_workspace");
   HIPCHK(hipStreamSynchronize(s), "set_workspace");
   return ENKFMC_OK;
 }
@@ -156,17 +188,24 @@ enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t 
   if (dtype != ENKFMC_F32 && dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "fit: bad dtype");
   if (ld < p->N) return fail(ENKFMC_EINVAL, "fit: ld < N");
   if (!(ridge >= 0.0) || ridge > 1e300) return fail(ENKFMC_EINVAL, "fit: ridge must be finite and >= 0");
-  if (mode != ENKFMC_FIT_PLAIN && mode != ENKFMC_FIT_BATCHED) return fail(ENKFMC_EINVAL, "fit: bad mode");
+  if (mode != ENKFMC_FIT_PLAIN && mode != ENKFMC_FIT_BATCHED && mode != ENKFMC_FIT_SVD)
+    return fail(ENKFMC_EINVAL, "fit: bad mode");
   hipStream_t s = (hipStream_t)stream;
   enkfmc_status st = begin(p, s, "fit");
   if (st != ENKFMC_OK) return st;
   p->fitted = p->analyzed = 0;
   const Dev d = make_dev(p);
   HIPCHK(launch_anomaly(p, d, Xb, dtype, ld, s), "fit: anomaly launch");
+  const bool plain_rows = mode == ENKFMC_FIT_PLAIN ||
+                          (mode == ENKFMC_FIT_BATCHED && p->bucket_off[kBucketPlain + 1] > p->bucket_off[kBucketPlain]);
+  if (plain_rows && !fit_plain_fits(p))
+    return fail(ENKFMC_EUNSUPPORTED, "fit: the plain kernel keeps an N x N Gram in LDS; N too large");
+  if (mode == ENKFMC_FIT_SVD && fit_svd_max_lds(p, ridge) > 160 * 1024)
+    return fail(ENKFMC_EUNSUPPORTED, "fit: SVD mode keeps each design matrix in LDS; regressions too large");
   if (mode == ENKFMC_FIT_PLAIN) {
-    if ((size_t)p->N * p->N * 8 + 8 * 1024 > 160 * 1024)
-      return fail(ENKFMC_EUNSUPPORTED, "fit: plain mode keeps an N x N Gram in LDS; N too large");
     HIPCHK(launch_fit_plain(p, d, ridge, s), "fit: plain launch");
+  } else if (mode == ENKFMC_FIT_SVD) {
+    HIPCHK(launch_fit_svd(p, d, ridge, s), "fit: svd launch");
   } else {
     HIPCHK(launch_fit_batched(p, d, ridge, s), "fit: batched launch");
   }
@@ -261,6 +300,12 @@ enkfmc_status enkfmc_analysis_sq_error_noalloc(int64_t n, int32_t N, const void 
   return ENKFMC_OK;
 }
 
+enkfmc_status enkfmc_rmse(const double *sq_err, int64_t M, double *out, void *stream) {
+  if (!sq_err || !out || M < 1) return fail(ENKFMC_EINVAL, "rmse: need M >= 1 squared errors and an output");
+  HIPCHK(launch_rmse(sq_err, M, out, (hipStream_t)stream), "rmse: launch");
+  return ENKFMC_OK;
+}
+
 enkfmc_status enkfmc_get_pattern_sizes(const enkfmc_plan *p, int32_t k, int64_t *n_sd, int64_t *nnz_sd,
                                        int64_t *m_sd) {
   if (!p || k < 0 || k >= (int32_t)p->subs.size()) return fail(ENKFMC_EINVAL, "get_pattern_sizes: bad sub-domain");
@@ -337,8 +382,43 @@ enkfmc_status enkfmc_get_increment(enkfmc_plan *p, int32_t k, double *Z, void *s
   return ENKFMC_OK;
 }
 
+enkfmc_status enkfmc_set_async(enkfmc_plan *p, int32_t enable) {
+  if (!p) return fail(ENKFMC_EINVAL, "set_async: NULL plan");
+  p->async = enable ? 1 : 0;
+  if (p->async) p->timing = 0;
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_check_status(enkfmc_plan *p, void *stream) {
+  if (!p) return fail(ENKFMC_EINVAL, "check_status: NULL plan");
+  if (!p->ws) return fail(ENKFMC_ESTATE, "check_status: no workspace");
+  hipStream_t s = (hipStream_t)stream;
+  int32_t st[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(st, p->ws + p->lay.status, sizeof(st), hipMemcpyDeviceToHost, s), "check_status");
+  HIPCHK(hipStreamSynchronize(s), "check_status");
+  if (st[0] != 0) HIPCHK(clear_status(p, s), "check_status");
+  return decode_status(st, "check_status");
+}
+
+enkfmc_status enkfmc_timestamp(uint64_t *dev, void *stream) {
+  if (!dev) return fail(ENKFMC_EINVAL, "timestamp: NULL argument");
+  hipLaunchKernelGGL(k_timestamp, dim3(1), dim3(64), 0, (hipStream_t)stream, dev);
+  HIPCHK(hipGetLastError(), "timestamp");
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_wall_clock_hz(int64_t *hz) {
+  if (!hz) return fail(ENKFMC_EINVAL, "wall_clock_hz: NULL argument");
+  int dev = 0, khz = 0;
+  HIPCHK(hipGetDevice(&dev), "wall_clock_hz");
+  HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall_clock_hz");
+  *hz = (int64_t)khz * 1000;
+  return ENKFMC_OK;
+}
+
 enkfmc_status enkfmc_set_timing(enkfmc_plan *p, int32_t enable) {
   if (!p) return fail(ENKFMC_EINVAL, "set_timing: NULL plan");
+  if (enable && p->async) return fail(ENKFMC_EINVAL, "set_timing: phase timing needs synchronous calls");
   if (enable && !p->ev[0]) {
     for (int i = 0; i < 2 * ENKFMC_PH_COUNT; ++i) {
       hipEvent_t e;

@@ -302,10 +302,10 @@ __global__ __launch_bounds__(256) void k_adj_regress(const Block *__restrict__ b
                                                      const double *__restrict__ tval, const double *__restrict__ dbar,
                                                      double *__restrict__ sb_io, double *__restrict__ e1,
                                                      double *__restrict__ e2, double *__restrict__ lam_row,
-                                                     int32_t *status) {
+                                                     int32_t *status, const int32_t *__restrict__ rows) {
   extern __shared__ double smem[];
   __shared__ int bad;
-  const int64_t r = blockIdx.x;
+  const int64_t r = rows ? (int64_t)rows[blockIdx.x] : (int64_t)blockIdx.x;
   const int tid = threadIdx.x;
   const Block B = blocks[fit_blk[r]];
   const int64_t lo = row_ptr[r];
@@ -627,6 +627,20 @@ __global__ __launch_bounds__(256) void k_adj_lambda(const double *__restrict__ v
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// The plain per-row adjoint (one workgroup per regression) over a list of fit
+// rows (every row when rows is NULL).
+hipError_t launch_adj_regress_plain_rows(enkfmc_plan *p, const Dev &d, double lam, const int32_t *rows,
+                                         int64_t nrows, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  const size_t lds = adj_regress_lds(p);
+  hipError_t e = hipFuncSetAttribute((const void *)k_adj_regress, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_regress, dim3((unsigned)nrows), dim3(256), lds, s, d.blocks, d.fit_glob, d.fit_blk,
+                     d.row_ptr, d.col, d.U, p->ldu, p->N, p->max_p, lam, d.tval, d.dbar, d.aux3, d.aux1, d.aux2,
+                     d.red, d.status, rows);
+  return hipGetLastError();
+}
+
 template <typename TX>
 static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int64_t ld, const double *Y,
                                  const double *r_diag, double lam, const double *dXa, double *dXb, double *dlogR,
@@ -660,15 +674,12 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   }
   phase_end(p, ENKFMC_PH_ADJ_FACTOR, s);
   phase_begin(p, ENKFMC_PH_ADJ_REGRESS, s);
-  if (p->fit_mode == ENKFMC_FIT_PLAIN || launch_adj_regress_batched(p, d, lam, s) == hipErrorNotSupported) {
-    // sizes beyond the one-wavefront kernels: one workgroup per regression
-    const size_t lds = adj_regress_lds(p);
-    e = hipFuncSetAttribute((const void *)k_adj_regress, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_regress, dim3((unsigned)p->n_fit), dim3(256), lds, s, d.blocks, d.fit_glob, d.fit_blk,
-                       d.row_ptr, d.col, d.U, p->ldu, N, p->max_p, lam, d.tval, d.dbar, d.aux3, d.aux1, d.aux2,
-                       d.red, d.status);
-  }
+  // the form of the preceding fit: the plain per-row adjoint after a plain
+  // fit, else the one-wavefront kernels per bucket (their plain bucket again
+  // per row)
+  e = p->fit_mode == ENKFMC_FIT_PLAIN ? launch_adj_regress_plain_rows(p, d, lam, nullptr, p->n_fit, s)
+                                      : launch_adj_regress_batched(p, d, lam, s);
+  if (e != hipSuccess) return e;
   phase_end(p, ENKFMC_PH_ADJ_REGRESS, s);
   phase_begin(p, ENKFMC_PH_ADJ_GATHER, s);
   const int mtu = max_block_tiles(p);

@@ -106,7 +106,22 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double *__restrict__ pa
   if (threadIdx.x == 0) out[0] = s;
 }
 
+// eq. (18): out = sqrt(sum_t e_t / M) over the M squared errors, summed in a
+// fixed order by one workgroup.
+__global__ __launch_bounds__(256) void k_rmse(const double *__restrict__ sq, int64_t M, double *__restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t t = threadIdx.x; t < M; t += 256) s += sq[t];
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) out[0] = sqrt(s / (double)M);
+}
+
 }  // namespace
+
+hipError_t launch_rmse(const double *sq, int64_t M, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rmse, dim3(1), dim3(256), 0, s, sq, M, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_perturb(const double *y, const double *r_diag, int64_t m, int N, uint64_t seed, uint64_t cycle,
                           double *Ys, hipStream_t s) {

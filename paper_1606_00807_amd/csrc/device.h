@@ -191,7 +191,14 @@ inline void phase_end(enkfmc_plan *p, int ph, hipStream_t s) {
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_anomaly(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, hipStream_t s);
 hipError_t launch_fit_plain(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
+hipError_t launch_fit_plain_rows(enkfmc_plan *p, const Dev &d, double lam, const int32_t *rows, int64_t nrows,
+                                 hipStream_t s);
+bool fit_plain_fits(const enkfmc_plan *p);   // the plain kernel's N x N Gram fits in LDS
+hipError_t launch_adj_regress_plain_rows(enkfmc_plan *p, const Dev &d, double lam, const int32_t *rows,
+                                         int64_t nrows, hipStream_t s);
 hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
+hipError_t launch_fit_svd(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
+size_t fit_svd_max_lds(const enkfmc_plan *p, double lam);   // LDS of the largest SVD regression
 hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s);
 int max_block_tiles(const enkfmc_plan *p);
 hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const double *V, double *out,
@@ -209,6 +216,7 @@ hipError_t launch_perturb(const double *y, const double *r_diag, int64_t m, int 
 constexpr int kSqErrorParts = 256;
 hipError_t launch_sq_error(const void *Xa, int32_t dtype, int64_t ld, int64_t n, int N, const double *xref,
                            double *part, double *out, hipStream_t s);
+hipError_t launch_rmse(const double *sq, int64_t M, double *out, hipStream_t s);
 // Device address of the current GPU's static scratch for those partials
 // (kSqErrorParts doubles), looked up once per device.
 hipError_t sq_error_scratch(double **out);

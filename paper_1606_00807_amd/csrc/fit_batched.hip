@@ -22,7 +22,11 @@
 //      kernel form: w = x, beta = U_P w, eps = mu w.   d = eps^T eps/(N-1).
 //
 // Every (T, form) pair is its own kernel, launched over a precomputed bucket
-// of rows, so that each kernel carries only the registers its T needs.
+// of rows, so that each kernel carries only the registers its T needs.  The
+// p-form kernels also take the largest member-tile count MT they unroll their
+// residual loops for (5 for N <= 80, else 8).  Systems up to T = 5 keep their
+// tiles in VGPRs; T = 6..8 run one wavefront per SIMD, with part of the tiles
+// held in AGPRs.
 //
 // The same routine, instantiated with ADJ, is the adjoint of a regression
 // (reverse pass of the fit).  Given Dbar = dL/dd and betabar = dL/dbeta of row
@@ -42,8 +46,8 @@ namespace enkfmc {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMaxT = 5;          // largest tile count handled here (m <= 80)
-constexpr int kMaxP = 128;        // largest predecessor count handled here
+constexpr int kMaxT = 8;          // largest tile count handled here (m <= 128, N <= 128)
+constexpr int kMaxP = 192;        // largest predecessor count handled here
 
 template <int T>
 struct WaveLds {                  // wavefront-private LDS (doubles unless noted)
@@ -316,7 +320,7 @@ __device__ __forceinline__ void adj_rhs(const int lane, const int64_t r, const i
   wave_lds_sync();
 }
 
-template <int T, bool KF, bool ADJ = false>
+template <int T, bool KF, int MT, bool ADJ = false>
 __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const int p, const int N, const double mu,
                                         const double *__restrict__ U, const int ldu, const int uoff, WaveLds<T> &L,
                                         double *__restrict__ tval, const int64_t lo, double *__restrict__ dvec,
@@ -636,7 +640,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     // predecessors a = q mod 4; the four partial sums are then added across q.
     for (int a = lane; a < p; a += 64) tval[lo + a] = -y[a];
     // one pointer per predecessor; the member tiles then differ by constant
-    // offsets (the loop over them is unrolled, N <= 16 kMaxT)
+    // offsets (the loop over them is unrolled, N <= 16 MT)
     double bq[4 * T];
     const double *up[4 * T];
 #pragma unroll
@@ -645,7 +649,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       up[j] = U + ((int64_t)L.pidx[4 * j + q] * ldu + c);
     }
 #pragma unroll
-    for (int I = 0; I < kMaxT; ++I) {
+    for (int I = 0; I < MT; ++I) {
       if (16 * I >= N) break;
       double e = 0.0;
 #pragma unroll
@@ -730,26 +734,26 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       // lane (q, c) sums members 16I + c over predecessors a = q mod 4, four
       // k-steps of loads at a time (pad row past p, columns 16I + c < ldu)
       const int nt = (N + 15) >> 4;
-      double e[kMaxT];
+      double e[MT];
 #pragma unroll
-      for (int I = 0; I < kMaxT; ++I) e[I] = 0.0;
+      for (int I = 0; I < MT; ++I) e[I] = 0.0;
       for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
-        double f[4][kMaxT], sv[4];
+        double f[4][MT], sv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int a = 4 * (ks0 + u) + q;
           const int off = L.pidx[a] * ldu + c;
           sv[u] = sl[a];
 #pragma unroll
-          for (int I = 0; I < kMaxT; ++I) f[u][I] = I < nt ? U[off + 16 * I] : 0.0;
+          for (int I = 0; I < MT; ++I) f[u][I] = I < nt ? U[off + 16 * I] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int I = 0; I < kMaxT; ++I) e[I] = fma(sv[u], f[u][I], e[I]);
+          for (int I = 0; I < MT; ++I) e[I] = fma(sv[u], f[u][I], e[I]);
       }
 #pragma unroll
-      for (int I = 0; I < kMaxT; ++I) {
+      for (int I = 0; I < MT; ++I) {
         if (I >= nt) break;
         double es = e[I];
         es = quarter_sum(es);
@@ -763,9 +767,9 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 }
 
 // waves per SIMD each kernel is compiled for (register budget 512 / occupancy)
-constexpr int occupancy_for(int T, bool KF) { return T <= 2 ? 4 : (T == 3 ? 4 : (T == 4 ? 3 : 2)); }
+constexpr int occupancy_for(int T, bool KF) { return T <= 3 ? 4 : (T == 4 ? 3 : (T == 5 ? 2 : 1)); }
 
-template <int T, bool KF>
+template <int T, bool KF, int MT>
 __global__ __launch_bounds__(256, occupancy_for(T, KF)) void k_fit_batched(
     const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
@@ -787,15 +791,17 @@ __global__ __launch_bounds__(256, occupancy_for(T, KF)) void k_fit_batched(
     if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
     return;
   }
-  fit_row<T, KF>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, dvec, status, AdjIO{});
+  fit_row<T, KF, MT>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, dvec, status, AdjIO{});
 }
 
 // Adjoint of the regressions of one bucket (same rows and shapes as the fit).
 // The adjoint carries the pre- and post-pass values too: one wave per SIMD less
 // for the larger kernel-form systems.
-constexpr int adj_occupancy_for(int T, bool KF) { return KF ? (T <= 2 ? 4 : (T == 3 ? 3 : 2)) : occupancy_for(T, KF); }
+constexpr int adj_occupancy_for(int T, bool KF) {
+  return KF ? (T <= 2 ? 4 : (T == 3 ? 3 : (T <= 5 ? 2 : 1))) : occupancy_for(T, KF);
+}
 
-template <int T, bool KF>
+template <int T, bool KF, int MT>
 __global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_batched(
     const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
@@ -816,7 +822,7 @@ __global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_b
   wave_lds_sync();
   AdjIO aw = adj;
   aw.ebl = ebl[wave];
-  fit_row<T, KF, true>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, nullptr, status, aw);
+  fit_row<T, KF, MT, true>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, nullptr, status, aw);
 }
 
 // Adjoint of the regressions without predecessors (eps = u).
@@ -855,89 +861,132 @@ __global__ __launch_bounds__(256) void k_fit_p0(const int32_t *__restrict__ fit_
   }
 }
 
-template <int T, bool KF>
+template <int T, bool KF, int MT>
 static void launch_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((k_fit_batched<T, KF>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d.blocks, d.fit_glob,
-                     d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam, d.tval, d.dvec,
-                     d.status);
+  hipLaunchKernelGGL((k_fit_batched<T, KF, MT>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d.blocks,
+                     d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam, d.tval,
+                     d.dvec, d.status);
 }
 
-// Whether a plan fits the batched kernels: systems up to 80 (N <= 80 in the
-// kernel form) and up to 128 predecessors fit their register budget, and
-// they address U (n + 2 rows of ldu doubles) with 32-bit element offsets.
-static bool batched_fits(const enkfmc_plan *p) {
-  return p->N <= 16 * kMaxT && p->max_p <= kMaxP && (int64_t)(p->n + 2) * p->ldu < (int64_t(1) << 31);
+// p-form bucket of T tiles: the residual loops unroll 5 member tiles when
+// N <= 80, else 8.
+template <int T>
+static void launch_pform(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam, hipStream_t s) {
+  if constexpr (T <= 5) {
+    if (p->N <= 80) return launch_bucket<T, false, 5>(p, d, rows, n, lam, s);
+  }
+  launch_bucket<T, false, 8>(p, d, rows, n, lam, s);
 }
 
 hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s) {
-  if (!batched_fits(p)) return launch_fit_plain(p, d, lam, s);   // the plain kernel takes any such plan
   phase_begin(p, ENKFMC_PH_FIT, s);
   const int32_t *rows = d.fit_rows;
-  const int64_t *bo = p->bucket_off;   // bucket 0: p = 0, 1..5: p-form T, 6: p >= N
-  if (bo[1] > bo[0])
-    hipLaunchKernelGGL(k_fit_p0, dim3((unsigned)((bo[1] - bo[0] + 3) / 4)), dim3(256), 0, s, d.fit_glob, d.U, p->ldu,
-                       p->N, rows + bo[0], bo[1] - bo[0], d.dvec, d.status);
-  launch_bucket<1, false>(p, d, rows + bo[1], bo[2] - bo[1], lam, s);
-  launch_bucket<2, false>(p, d, rows + bo[2], bo[3] - bo[2], lam, s);
-  launch_bucket<3, false>(p, d, rows + bo[3], bo[4] - bo[3], lam, s);
-  launch_bucket<4, false>(p, d, rows + bo[4], bo[5] - bo[4], lam, s);
-  launch_bucket<5, false>(p, d, rows + bo[5], bo[6] - bo[5], lam, s);
-  const int64_t nk = bo[7] - bo[6];
-  if (lam > 0.0) {
-    if (nk > 0) phase_begin(p, ENKFMC_PH_FIT_KFORM, s);
-    switch ((p->N + 15) / 16) {   // kernel form: m = N
-      case 1: launch_bucket<1, true>(p, d, rows + bo[6], nk, lam, s); break;
-      case 2: launch_bucket<2, true>(p, d, rows + bo[6], nk, lam, s); break;
-      case 3: launch_bucket<3, true>(p, d, rows + bo[6], nk, lam, s); break;
-      case 4: launch_bucket<4, true>(p, d, rows + bo[6], nk, lam, s); break;
-      default: launch_bucket<5, true>(p, d, rows + bo[6], nk, lam, s); break;
+  const int64_t *bo = p->bucket_off;   // see kBucket* in plan.h
+  if (bo[kBucketP0 + 1] > bo[kBucketP0])
+    hipLaunchKernelGGL(k_fit_p0, dim3((unsigned)((bo[kBucketP0 + 1] - bo[kBucketP0] + 3) / 4)), dim3(256), 0, s,
+                       d.fit_glob, d.U, p->ldu, p->N, rows + bo[kBucketP0], bo[kBucketP0 + 1] - bo[kBucketP0], d.dvec,
+                       d.status);
+  auto nb = [&](int b) { return bo[b + 1] - bo[b]; };
+  launch_pform<1>(p, d, rows + bo[1], nb(1), lam, s);
+  launch_pform<2>(p, d, rows + bo[2], nb(2), lam, s);
+  launch_pform<3>(p, d, rows + bo[3], nb(3), lam, s);
+  launch_pform<4>(p, d, rows + bo[4], nb(4), lam, s);
+  launch_pform<5>(p, d, rows + bo[5], nb(5), lam, s);
+  launch_pform<6>(p, d, rows + bo[6], nb(6), lam, s);
+  launch_pform<7>(p, d, rows + bo[7], nb(7), lam, s);
+  launch_pform<8>(p, d, rows + bo[8], nb(8), lam, s);
+  const int64_t nk = nb(kBucketKF);
+  const int32_t *rk = rows + bo[kBucketKF];
+  if (nk > 0) {
+    // kernel form: m = N.  Without a ridge these rows (p >= N) are ENOTSPD,
+    // which the p-form kernel reports before any arithmetic.
+    if (lam > 0.0) {
+      phase_begin(p, ENKFMC_PH_FIT_KFORM, s);
+      switch ((p->N + 15) / 16) {
+        case 1: launch_bucket<1, true, 1>(p, d, rk, nk, lam, s); break;
+        case 2: launch_bucket<2, true, 2>(p, d, rk, nk, lam, s); break;
+        case 3: launch_bucket<3, true, 3>(p, d, rk, nk, lam, s); break;
+        case 4: launch_bucket<4, true, 4>(p, d, rk, nk, lam, s); break;
+        case 5: launch_bucket<5, true, 5>(p, d, rk, nk, lam, s); break;
+        case 6: launch_bucket<6, true, 6>(p, d, rk, nk, lam, s); break;
+        case 7: launch_bucket<7, true, 7>(p, d, rk, nk, lam, s); break;
+        default: launch_bucket<8, true, 8>(p, d, rk, nk, lam, s); break;
+      }
+      phase_end(p, ENKFMC_PH_FIT_KFORM, s);
+    } else {
+      launch_bucket<1, false, 8>(p, d, rk, nk, lam, s);
     }
-    if (nk > 0) phase_end(p, ENKFMC_PH_FIT_KFORM, s);
-  } else {
-    launch_bucket<5, false>(p, d, rows + bo[6], nk, lam, s);   // p >= N without ridge: ENOTSPD
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // rows no one-wavefront kernel takes: the plain kernel, on those rows only
+  if (nb(kBucketPlain) > 0) {
+    phase_begin(p, ENKFMC_PH_FIT_FALLBACK, s);
+    e = launch_fit_plain_rows(p, d, lam, d.fit_rows + bo[kBucketPlain], nb(kBucketPlain), s);
+    phase_end(p, ENKFMC_PH_FIT_FALLBACK, s);
+    if (e != hipSuccess) return e;
   }
   phase_end(p, ENKFMC_PH_FIT, s);
   return hipGetLastError();
 }
 
-
-template <int T, bool KF>
+template <int T, bool KF, int MT>
 static void launch_adj_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam,
                               const AdjIO &adj, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((k_adj_regress_batched<T, KF>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d.blocks,
-                     d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam, d.tval, adj,
-                     d.status);
+  hipLaunchKernelGGL((k_adj_regress_batched<T, KF, MT>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d.blocks,
+                     d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam, d.tval,
+                     adj, d.status);
 }
 
-// Adjoint of every regression over the fit's buckets.  hipErrorNotSupported
-// when the sizes exceed this kernel (the caller then uses the plain form).
+template <int T>
+static void launch_adj_pform(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam,
+                             const AdjIO &adj, hipStream_t s) {
+  if constexpr (T <= 5) {
+    if (p->N <= 80) return launch_adj_bucket<T, false, 5>(p, d, rows, n, lam, adj, s);
+  }
+  launch_adj_bucket<T, false, 8>(p, d, rows, n, lam, adj, s);
+}
+
+// Adjoint of every regression over the fit's buckets; the rows of the plain
+// bucket go to the plain per-row adjoint.
 hipError_t launch_adj_regress_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s) {
-  if (!batched_fits(p)) return hipErrorNotSupported;
   const AdjIO adj{d.dbar, d.aux3, d.aux1, d.aux2, d.red};
   const int32_t *rows = d.fit_rows;
   const int64_t *bo = p->bucket_off;
-  if (bo[1] > bo[0])
-    hipLaunchKernelGGL(k_adj_p0, dim3((unsigned)((bo[1] - bo[0] + 3) / 4)), dim3(256), 0, s, d.fit_glob, d.U, p->ldu,
-                       p->N, rows + bo[0], bo[1] - bo[0], adj);
-  launch_adj_bucket<1, false>(p, d, rows + bo[1], bo[2] - bo[1], lam, adj, s);
-  launch_adj_bucket<2, false>(p, d, rows + bo[2], bo[3] - bo[2], lam, adj, s);
-  launch_adj_bucket<3, false>(p, d, rows + bo[3], bo[4] - bo[3], lam, adj, s);
-  launch_adj_bucket<4, false>(p, d, rows + bo[4], bo[5] - bo[4], lam, adj, s);
-  launch_adj_bucket<5, false>(p, d, rows + bo[5], bo[6] - bo[5], lam, adj, s);
-  const int64_t nk = bo[7] - bo[6];
+  auto nb = [&](int b) { return bo[b + 1] - bo[b]; };
+  if (nb(kBucketP0) > 0)
+    hipLaunchKernelGGL(k_adj_p0, dim3((unsigned)((nb(kBucketP0) + 3) / 4)), dim3(256), 0, s, d.fit_glob, d.U,
+                       p->ldu, p->N, rows + bo[kBucketP0], nb(kBucketP0), adj);
+  launch_adj_pform<1>(p, d, rows + bo[1], nb(1), lam, adj, s);
+  launch_adj_pform<2>(p, d, rows + bo[2], nb(2), lam, adj, s);
+  launch_adj_pform<3>(p, d, rows + bo[3], nb(3), lam, adj, s);
+  launch_adj_pform<4>(p, d, rows + bo[4], nb(4), lam, adj, s);
+  launch_adj_pform<5>(p, d, rows + bo[5], nb(5), lam, adj, s);
+  launch_adj_pform<6>(p, d, rows + bo[6], nb(6), lam, adj, s);
+  launch_adj_pform<7>(p, d, rows + bo[7], nb(7), lam, adj, s);
+  launch_adj_pform<8>(p, d, rows + bo[8], nb(8), lam, adj, s);
+  const int64_t nk = nb(kBucketKF);
+  const int32_t *rk = rows + bo[kBucketKF];
   if (nk > 0) {
     if (!(lam > 0.0)) return hipErrorInvalidValue;   // the fit rejects p >= N - 1 without ridge
     switch ((p->N + 15) / 16) {
-      case 1: launch_adj_bucket<1, true>(p, d, rows + bo[6], nk, lam, adj, s); break;
-      case 2: launch_adj_bucket<2, true>(p, d, rows + bo[6], nk, lam, adj, s); break;
-      case 3: launch_adj_bucket<3, true>(p, d, rows + bo[6], nk, lam, adj, s); break;
-      case 4: launch_adj_bucket<4, true>(p, d, rows + bo[6], nk, lam, adj, s); break;
-      default: launch_adj_bucket<5, true>(p, d, rows + bo[6], nk, lam, adj, s); break;
+      case 1: launch_adj_bucket<1, true, 1>(p, d, rk, nk, lam, adj, s); break;
+      case 2: launch_adj_bucket<2, true, 2>(p, d, rk, nk, lam, adj, s); break;
+      case 3: launch_adj_bucket<3, true, 3>(p, d, rk, nk, lam, adj, s); break;
+      case 4: launch_adj_bucket<4, true, 4>(p, d, rk, nk, lam, adj, s); break;
+      case 5: launch_adj_bucket<5, true, 5>(p, d, rk, nk, lam, adj, s); break;
+      case 6: launch_adj_bucket<6, true, 6>(p, d, rk, nk, lam, adj, s); break;
+      case 7: launch_adj_bucket<7, true, 7>(p, d, rk, nk, lam, adj, s); break;
+      default: launch_adj_bucket<8, true, 8>(p, d, rk, nk, lam, adj, s); break;
     }
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (nb(kBucketPlain) > 0) return launch_adj_regress_plain_rows(p, d, lam, rows + bo[kBucketPlain],
+                                                                 nb(kBucketPlain), s);
+  return hipSuccess;
 }
 
 }  // namespace enkfmc

@@ -53,10 +53,11 @@ __global__ __launch_bounds__(256) void k_fit_plain(const Block *__restrict__ blo
                                                    const int64_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const double *__restrict__ U,
                                                    int ldu, int N, int max_p, double lam, double *__restrict__ tval,
-                                                   double *__restrict__ dvec, int32_t *status) {
+                                                   double *__restrict__ dvec, int32_t *status,
+                                                   const int32_t *__restrict__ rows) {
   extern __shared__ double smem[];
   __shared__ int bad;
-  const int64_t r = blockIdx.x;
+  const int64_t r = rows ? (int64_t)rows[blockIdx.x] : (int64_t)blockIdx.x;
   const int tid = threadIdx.x;
   const Block B = blocks[fit_blk[r]];
   const int64_t lo = row_ptr[r];
@@ -187,15 +188,25 @@ size_t fit_plain_lds(const enkfmc_plan *p) {
   return (size_t)N * N * 8 + (size_t)(N > mp ? N : mp) * 8 + 8 * 8 + (size_t)mp * 4 + 16;
 }
 
-hipError_t launch_fit_plain(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s) {
+bool fit_plain_fits(const enkfmc_plan *p) { return fit_plain_lds(p) <= 160 * 1024; }
+
+// The plain kernel over a list of fit rows (every row when rows is NULL).
+hipError_t launch_fit_plain_rows(enkfmc_plan *p, const Dev &d, double lam, const int32_t *rows, int64_t nrows,
+                                 hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
   const size_t lds = fit_plain_lds(p);
   hipError_t e = hipFuncSetAttribute((const void *)k_fit_plain, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  phase_begin(p, ENKFMC_PH_FIT, s);
-  hipLaunchKernelGGL(k_fit_plain, dim3((unsigned)p->n_fit), dim3(256), lds, s, d.blocks, d.fit_glob, d.fit_blk,
-                     d.row_ptr, d.col, d.U, p->ldu, p->N, p->max_p, lam, d.tval, d.dvec, d.status);
-  phase_end(p, ENKFMC_PH_FIT, s);
+  hipLaunchKernelGGL(k_fit_plain, dim3((unsigned)nrows), dim3(256), lds, s, d.blocks, d.fit_glob, d.fit_blk,
+                     d.row_ptr, d.col, d.U, p->ldu, p->N, p->max_p, lam, d.tval, d.dvec, d.status, rows);
   return hipGetLastError();
+}
+
+hipError_t launch_fit_plain(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s) {
+  phase_begin(p, ENKFMC_PH_FIT, s);
+  const hipError_t e = launch_fit_plain_rows(p, d, lam, nullptr, p->n_fit, s);
+  phase_end(p, ENKFMC_PH_FIT, s);
+  return e;
 }
 
 }  // namespace enkfmc

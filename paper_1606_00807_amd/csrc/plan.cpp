@@ -126,21 +126,23 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
   for (int64_t gi = 0; gi < n; ++gi)
     if (p->interior_src[gi] < 0) { *err = "internal: component not covered by any interior"; return ENKFMC_EINVAL; }
 
-  // regressions grouped by size for the batched fit (stable within a group)
+  // regressions grouped by the kernel that fits them (stable within a group)
   {
+    const bool offsets_fit = (n + 2) * (int64_t)p->ldu < (int64_t(1) << 31);   // 32-bit offsets into U
     auto key = [&](int64_t r) {
       const int64_t pp = p->row_ptr[r + 1] - p->row_ptr[r];
-      if (pp == 0) return 0;
-      if (pp >= N) return 6;
-      return (int)std::min<int64_t>((pp + 15) / 16, 5);
+      if (pp == 0) return kBucketP0;
+      if (!offsets_fit || N > kBatchedMaxN || pp > kBatchedMaxP) return kBucketPlain;
+      if (pp >= N) return kBucketKF;
+      return (int)((pp + 15) / 16);   // p < N <= 128: 1..8 tiles
     };
-    int64_t cnt[8] = {};
+    int64_t cnt[kBuckets + 1] = {};
     for (int64_t r = 0; r < n_fit; ++r) cnt[key(r) + 1]++;
-    for (int b = 0; b < 7; ++b) cnt[b + 1] += cnt[b];
-    for (int b = 0; b < 8; ++b) p->bucket_off[b] = cnt[b];
+    for (int b = 0; b < kBuckets; ++b) cnt[b + 1] += cnt[b];
+    for (int b = 0; b <= kBuckets; ++b) p->bucket_off[b] = cnt[b];
     p->fit_rows.assign(n_fit, 0);
-    int64_t fill[8];
-    for (int b = 0; b < 8; ++b) fill[b] = cnt[b];
+    int64_t fill[kBuckets];
+    for (int b = 0; b < kBuckets; ++b) fill[b] = cnt[b];
     for (int64_t r = 0; r < n_fit; ++r) p->fit_rows[fill[key(r)]++] = (int32_t)r;
   }
 

@@ -30,6 +30,16 @@ struct Block {
   int64_t ot0;           // first observation tile (global numbering; ldf / 16 tiles)
 };
 
+// Buckets of the batched fit: rows grouped by the kernel that fits them.
+constexpr int kBucketP0 = 0;      // no predecessors: d = u^T u / (N - 1)
+                                  // 1..8: p < N, ceil(p/16) tiles (p-form)
+constexpr int kBucketKF = 9;      // p >= N: kernel form, N x N system
+constexpr int kBucketPlain = 10;  // beyond the one-wavefront kernels (N > 128, p > 192, or
+                                  // 32-bit offsets into U would overflow): the plain kernel
+constexpr int kBuckets = 11;
+constexpr int kBatchedMaxN = 128;  // largest N of the one-wavefront kernels
+constexpr int kBatchedMaxP = 192;  // largest predecessor count of the one-wavefront kernels
+
 struct SubBox {
   int32_t kx, ky, x0, x1, y0, y1, xs, BX, ys, BY, ring;
   int32_t blk0;          // first block of the sub-domain
@@ -59,7 +69,7 @@ struct enkfmc_plan {
   std::vector<enkfmc::Block> blocks;
   std::vector<int32_t> fit_glob, fit_blk;       // per fit row
   std::vector<int32_t> fit_rows;                // fit rows grouped by regression size (see bucket_off)
-  int64_t bucket_off[8] = {};                   // 0: p = 0, 1..5: p < N with ceil(p/16), 6: p >= N
+  int64_t bucket_off[enkfmc::kBuckets + 1] = {};        // rows of bucket b: fit_rows[bucket_off[b], bucket_off[b + 1])
   std::vector<int64_t> row_ptr;                 // n_fit + 1, global CSR offsets
   std::vector<int32_t> col;                     // block-local predecessor rows
   std::vector<int64_t> csc_ptr;                 // n_fit + 1, transposed pattern
@@ -99,6 +109,7 @@ struct enkfmc_plan {
   const void *an_y = nullptr, *an_r = nullptr;  // Y and r_diag of the last analysis
   // optional per-phase timing with HIP events on the call's stream
   int32_t timing = 0;
+  int32_t async = 0;               // calls neither clear nor read the status word (enkfmc_set_async)
   void *ev[64] = {};
   uint64_t recorded = 0;
   double phase_ms[32] = {};

@@ -9,10 +9,11 @@ one); every other step runs in libenkfmc.so.
 """
 from __future__ import annotations
 
-import math
+import ctypes
 from dataclasses import dataclass
 from typing import Callable, List, Optional, Sequence
 
+from . import _lib
 from .api import Plan
 
 
@@ -23,13 +24,18 @@ class CycleResult:
     rmse: Optional[float]      # eq. (18), or None without reference states
 
 
-def rmse(sq_err: Sequence[float]) -> float:
+def rmse(sq_err) -> float:
     """eq. (18): sqrt of the mean over the M assimilation times of the squared
-    error of the analysis mean."""
-    vals = [float(v) for v in sq_err]
-    if not vals:
+    error of the analysis mean, computed by the library (enkfmc_rmse) from a
+    CUDA tensor (or a sequence, copied to the device) of the M squared errors."""
+    import torch
+    sq = torch.as_tensor(sq_err, dtype=torch.float64).to("cuda").contiguous().reshape(-1)
+    if sq.numel() == 0:
         raise ValueError("rmse needs at least one assimilation time")
-    return math.sqrt(math.fsum(vals) / len(vals))
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    _lib.check(_lib.load().enkfmc_rmse(ctypes.c_void_p(sq.data_ptr()), sq.numel(), ctypes.c_void_p(out.data_ptr()),
+                                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return float(out.item())
 
 
 def assimilate(plan: Plan, Xb, observations: Sequence, r_diag, ridge: float,
@@ -65,4 +71,4 @@ def assimilate(plan: Plan, Xb, observations: Sequence, r_diag, ridge: float,
     if x_ref is None:
         return CycleResult(Xa, None, None)
     sq = torch.cat(errs)
-    return CycleResult(Xa, sq, rmse(sq.cpu().tolist()))
+    return CycleResult(Xa, sq, rmse(sq))

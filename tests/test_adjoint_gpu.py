@@ -131,6 +131,24 @@ def test_autograd_function_matches_direct_backward():
     assert torch.equal(Xb.grad, dXb) and torch.equal(logr.grad, dlogR) and torch.equal(lam.grad, dlam.reshape(()))
 
 
+def test_autograd_refuses_observations_overwritten_in_place():
+    """The reverse pass reads the Y of its forward call: refilling that
+    tensor in place before backward() must raise, not give gradients of
+    another analysis."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    p = CASES["mixed_forms"]()
+    plan = Plan(p.geometry, p.N, p.obs_idx)
+    Xb = torch.as_tensor(p.Xb).cuda().requires_grad_(True)
+    logr = torch.log(torch.as_tensor(p.r_diag)).cuda().requires_grad_(True)
+    Y = torch.as_tensor(p.Y).cuda()
+    Xa = enkfmc_analysis(Xb, logr, p.ridge, plan, Y)
+    loss = torch.sum(Xa ** 2)
+    Y.add_(1.0)   # e.g. the next cycle's perturbed observations drawn into the same buffer
+    with pytest.raises(RuntimeError, match="modified by an inplace operation"):
+        loss.backward()
+
+
 def test_backward_without_analysis_is_a_state_error():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

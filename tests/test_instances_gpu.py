@@ -2,9 +2,11 @@
 32x16 to 192x96, 1-7 levels, N in [20, 120], r in [1, 5], 2-30% observed,
 ridge 1e-3, 8 x 8-point sub-domains.
 
-These instances reach sizes the T-63 workload does not: N > 80 and more than
-128 predecessors (the plain fit and its adjoint), and blocks with more than
-128 observations (several observation tiles per dual-form wavefront).
+These instances reach sizes the T-63 workload does not: N up to 120 and up
+to 181 predecessors (systems of 6-8 tiles in the one-wavefront fit and its
+adjoint), and blocks with more than 128 observations (several observation
+tiles per dual-form wavefront).  Every regression of every instance must run
+on the one-wavefront kernels (none in the plain fallback bucket).
 
 Every instance runs whole on the GPU.  The oracle recomputes one sampled
 sub-domain per instance (T, D, local increments, X_a on its interior), and the
@@ -45,7 +47,9 @@ def test_instance_sampled_subdomain_matches_oracle(k):
     d = PARAMS[k]
     plan = Plan(p.geometry, p.N, p.obs_idx)
     _say(f"[instance {k}] {d['nx']}x{d['ny']}x{d['nlev']} N={p.N} r={d['r']} m={p.m} "
-         f"max_p={plan.info['max_p']} max_block_obs={plan.info['max_block_obs']}")
+         f"max_p={plan.info['max_p']} max_block_obs={plan.info['max_block_obs']} "
+         f"rows wave/plain={plan.info['fit_rows_wave']}/{plan.info['fit_rows_plain']}")
+    assert plan.info["fit_rows_plain"] == 0 and plan.info["fit_rows_wave"] == plan.info["n_fit"]
     Xb = torch.as_tensor(p.Xb).cuda()
     plan.fit(Xb, p.ridge, mode="batched")
     Xa = plan.analyze(Xb, p.Y, p.r_diag).cpu().numpy()
@@ -67,8 +71,9 @@ def test_instance_sampled_subdomain_matches_oracle(k):
     assert et <= 1e-9 and ed <= 1e-9 and ez <= 1e-8 and em <= 1e-6
 
 
-# small instances that cover N > 80, p > 128 and blocks with > 128 observations
-@pytest.mark.parametrize("k", [1, 7, 20, 52])
+# instances that cover N > 80 (up to 120: 8-tile kernel-form and p-form
+# systems in instance 54), p > 128 and blocks with > 128 observations
+@pytest.mark.parametrize("k", [1, 7, 20, 52, 54])
 def test_instance_adjoint_matches_oracle(k):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -76,6 +81,7 @@ def test_instance_adjoint_matches_oracle(k):
     plan = Plan(p.geometry, p.N, p.obs_idx)
     _say(f"[instance {k} adjoint] n={p.n} N={p.N} m={p.m} max_p={plan.info['max_p']} "
          f"max_block_obs={plan.info['max_block_obs']}")
+    assert plan.info["fit_rows_plain"] == 0
     res = A.analyze(p.geometry, p.Xb, p.Y, p.obs_idx, p.r_diag, p.ridge)
     G = 2.0 * (res.Xa - p.x_true[:, None])
     dXb_o, dlogR_o, dlam_o = J.analyze_backward(p.Xb, p.obs_idx, p.r_diag, p.ridge, res, G)

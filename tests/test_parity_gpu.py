@@ -42,7 +42,24 @@ CASES = {
     "fp32_storage": lambda: synth.make_small(nx=12, ny=10, nlev=(3,), N=24, r_h=1, r_v=1, sdx=2, sdy=2,
                                              obs_frac=0.3, ridge=1e-3, config=205, dtype=np.float32),
     "grid96x48": lambda: synth.make_grid2d(),
+    # p-form systems of 6-8 tiles (p up to 121 < N = 125)
+    "pform_8tiles": lambda: synth.make_small(nx=16, ny=10, nlev=(3,), N=125, r_h=4, r_v=1, sdx=2, sdy=2,
+                                             obs_frac=0.2, ridge=1e-3, config=208),
+    # kernel-form systems of 8 tiles (N = 120, p up to 181)
+    "kform_8tiles": lambda: synth.make_small(nx=20, ny=12, nlev=(3,), N=120, r_h=5, r_v=1, sdx=2, sdy=2,
+                                             obs_frac=0.2, ridge=1e-3, config=209),
+    # rows with more than 192 predecessors (r_h = 4, r_v = 2: up to 202) go to
+    # the plain kernel, the others to the one-wavefront kernels
+    "plain_bucket_p": lambda: synth.make_small(nx=12, ny=12, nlev=(5,), N=40, r_h=4, r_v=2, sdx=1, sdy=1,
+                                               obs_frac=0.2, ridge=1e-2, config=210),
+    # N > 128: every row with predecessors goes to the plain kernel
+    "plain_bucket_N": lambda: synth.make_small(nx=10, ny=8, nlev=(2,), N=136, r_h=1, r_v=1, sdx=2, sdy=2,
+                                               obs_frac=0.3, ridge=1e-3, config=211),
 }
+
+# expected split of the batched fit between the one-wavefront kernels and
+# the plain fallback bucket
+SPLIT = {"plain_bucket_p": "both", "plain_bucket_N": "both"}
 
 
 def _rel(a, b):
@@ -75,6 +92,17 @@ def test_fit_and_analysis_match_oracle(case, mode):
         worst_d = max(worst_d, float(np.max(np.abs(d - fac.d) / fac.d)))
         if np.any(Z):
             worst_z = max(worst_z, _rel(plan.increment(k), Z))
+    info = plan.info
+    if case in SPLIT:
+        assert info["fit_rows_plain"] > 0 and info["fit_rows_wave"] > 0, info
+    else:
+        assert info["fit_rows_plain"] == 0 and info["fit_rows_wave"] == info["n_fit"], info
+    if mode == "batched":   # the timing of the last fit names the kernels that ran
+        plan.set_timing(True)
+        plan.fit(torch.as_tensor(p.Xb).cuda(), p.ridge, mode=mode)
+        ph = plan.timing()
+        plan.set_timing(False)
+        assert (ph["fit_fallback"] > 0) == (case in SPLIT), ph
     mean_rel = float(np.linalg.norm(Xa.mean(1) - res.Xa.mean(1)) / np.linalg.norm(res.Xa.mean(1)))
     inc_rel = float(np.linalg.norm((Xa - res.Xa)) / max(np.linalg.norm(res.Xa - p.Xb), 1e-300))
     _say(f"[parity] case={case} mode={mode} T={worst_t:.2e} D={worst_d:.2e} Z={worst_z:.2e} "
