@@ -65,6 +65,225 @@ def traffic_per_launch():
     return TRAFFIC["bytes_per_launch"]
 
 
+# ---------------------------------------------------------------- CPU baseline
+# The oracle (plain FP64 NumPy/SciPy, as it stands) on the host's cores: one
+# worker process per core, each with its BLAS limited to one thread, each
+# generating the same seeded workload once (not timed) and then fitting and
+# solving whole sub-domains.  The workers are started before the parent
+# touches the GPU.
+_W = {}
+
+
+def _cpu_worker_init(barrier):
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+
+    import synth
+    from oracle import fit as OF
+    _W["limits"] = threadpool_limits(1)
+    prob = synth.make_t63()
+    _W["prob"] = prob
+    _W["U"] = OF.anomalies(prob.Xb)[1]
+    _W["X64"] = np.asarray(prob.Xb, np.float64)
+    barrier.wait()
+
+
+def _cpu_worker_subdomain(k):
+    from oracle import analysis as OA
+    from oracle import fit as OF
+    from oracle import geometry as OG
+    prob = _W["prob"]
+    pat = OG.subdomain_pattern(prob.geometry, k, prob.obs_idx)
+    t = time.perf_counter()
+    fac = OF.fit_subdomain(_W["U"], pat, prob.ridge)
+    innov = OA.innovations(_W["X64"], prob.Y, prob.obs_idx, pat)
+    Z = OA.solve_subdomain(fac, innov, prob.r_diag)
+    dt = time.perf_counter() - t
+    return k, os.getpid(), dt, pat.loc2glob[pat.interior], Z[pat.interior]
+
+
+def start_cpu_pool(max_workers: int = 16):
+    """Spawn one oracle worker per core of this process's affinity (at most
+    max_workers, the host share of one GPU); returns (pool, workers, affinity)."""
+    import multiprocessing as mp
+    affinity = len(os.sched_getaffinity(0))
+    workers = max(1, min(affinity, max_workers))
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(workers + 1)
+    pool = ctx.Pool(workers, initializer=_cpu_worker_init, initargs=(barrier,))
+    return pool, workers, affinity, barrier
+
+
+def host_description():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        info = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+        if info:
+            blas = f"{info[0].get('internal_api')} {info[0].get('version')} ({info[0].get('architecture')})"
+    except Exception:
+        pass
+    return model, blas
+
+
+def cpu_baseline(pool, workers, affinity, prob, Xa_h, n_sub):
+    """Oracle fit + local solve of n_sub whole sub-domains spread over the
+    workers; returns the baseline record and the GPU-vs-oracle errors on them."""
+    import numpy as np
+    g = np.random.default_rng(0)
+    nsd = prob.geometry["sdx"] * prob.geometry["sdy"]
+    ks = [0, 24 * 6 + 11] + sorted(g.choice(np.arange(1, nsd - 1), n_sub - 2, replace=False).tolist())
+    X64 = np.asarray(prob.Xb, np.float64)
+    busy = {}
+    diff2 = ref2 = 0.0
+    comps = 0
+    maxabs = 0.0
+    t0 = time.perf_counter()
+    for k, pid, dt, rows, Zi in pool.imap_unordered(_cpu_worker_subdomain, ks, chunksize=1):
+        busy[pid] = busy.get(pid, 0.0) + dt
+        xa_ref = X64[rows] + Zi
+        comps += rows.size
+        diff2 += float(np.sum((Xa_h[rows].mean(1) - xa_ref.mean(1)) ** 2))
+        ref2 += float(np.sum(xa_ref.mean(1) ** 2))
+        maxabs = max(maxabs, float(np.max(np.abs(Xa_h[rows] - xa_ref))))
+    wall = time.perf_counter() - t0
+    span = max(busy.values())   # busiest worker: fit + solve time, the planner excluded
+    model, blas = host_description()
+    rec = {"value": comps / span, "unit": "components/s", "cores": workers, "kind": "oracle",
+           "sample": f"{len(ks)} of {nsd} sub-domains (fit of all their local rows + local solves), {comps} "
+                     f"interior components, spread over {workers} worker processes (one per core, BLAS 1 thread "
+                     f"each); busiest worker {span:.1f}s of fit + solve, {sum(busy.values()):.1f} core-s in all, "
+                     f"{wall:.1f}s wall with the planner",
+           "affinity_cores": affinity, "cpu_model": model, "blas": blas}
+    return rec, float(np.sqrt(diff2 / ref2)), maxabs
+
+
+def small_config(name, mode_steps=20):
+    """Fit + analysis of a small workload (ring40, grid96x48): batched and plain
+    FP64 times and the analysis-mean error against the whole oracle analysis."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import analysis as OA
+    from paper_1606_00807_amd import Plan
+    p = synth.make_ring() if name == "ring40" else synth.make_grid2d()
+    plan = Plan(p.geometry, p.N, p.obs_idx)
+    Xb = torch.as_tensor(p.Xb).cuda()
+    Y = torch.as_tensor(p.Y).cuda()
+    r = torch.as_tensor(p.r_diag).cuda()
+    out = {"n": p.n, "N": p.N, "m": p.m, "sub_domains": p.geometry["sdx"] * p.geometry["sdy"]}
+    ref = OA.analyze(p.geometry, p.Xb, p.Y, p.obs_idx, p.r_diag, p.ridge)
+    for mode in ("batched", "plain"):
+        for _ in range(3):
+            plan.fit(Xb, p.ridge, mode=mode)
+            Xa = plan.analyze(Xb, Y, r)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(mode_steps):
+            plan.fit(Xb, p.ridge, mode=mode)
+            Xa = plan.analyze(Xb, Y, r)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / mode_steps
+        Xa_h = Xa.cpu().numpy()
+        rel = float(np.linalg.norm(Xa_h.mean(1) - ref.Xa.mean(1)) / np.linalg.norm(ref.Xa.mean(1)))
+        out[mode] = {"ms_per_step": dt * 1e3, "components_per_s": p.n / dt, "rel_err_mean_vs_oracle": rel}
+    out["speedup_vs_plain"] = out["plain"]["ms_per_step"] / out["batched"]["ms_per_step"]
+    out["note"] = ("each step is enkfmc_fit + enkfmc_analyze, both ending in a device-to-host status read, so at "
+                   "these sizes the figure is launch latency")
+    plan.close()
+    return out
+
+
+def c5_bench(replays: int, branches: int) -> dict:
+    """The uneven batch: 64 independent instances (grids 32x16 to 192x96, 1-7
+    levels, N 20-120, r 1-5, 2-30% observed), fit + analysis of all of them in
+    one captured HIP graph; aggregate components/s over the graph replay and
+    per-instance latency from device timestamps (p50 / p99 over instances,
+    each instance's median over the replays).  Batched and plain FP64 fits,
+    each in its own graph; the batched outputs checked against the oracle on
+    one sampled sub-domain of every instance."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import analysis as OA
+    from oracle import fit as OF
+    from oracle import geometry as OG
+    from paper_1606_00807_amd import Plan
+    from paper_1606_00807_amd.graph import InstanceGraph
+
+    params = synth.instance_params()
+    probs = [synth.make_instance(k, params) for k in range(len(params))]
+    n_tot = sum(p.n for p in probs)
+    out = {"instances": len(probs), "n_total": n_tot, "branches": branches}
+    for mode in ("batched", "plain"):
+        items = []
+        for p in probs:
+            plan = Plan(p.geometry, p.N, p.obs_idx)
+            items.append(dict(plan=plan, Xb=torch.as_tensor(p.Xb).cuda(), Y=torch.as_tensor(p.Y).cuda(),
+                              r_diag=torch.as_tensor(p.r_diag).cuda(), ridge=p.ridge, mode=mode))
+        # batched: the captured graph; plain: the same enqueue order run
+        # without a graph (asynchronous plans on the same branch streams)
+        g = InstanceGraph(items, branches=branches)
+        g.run_eager()
+        if mode == "batched":
+            g.capture()
+            g.replay()
+            torch.cuda.synchronize()
+        run = g.replay if mode == "batched" else g._enqueue
+        reps = replays if mode == "batched" else max(1, replays // 5)
+        lat = []
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tot = 0.0
+        for _ in range(reps):
+            ev0.record()
+            run()
+            ev1.record()
+            torch.cuda.synchronize()
+            tot += ev0.elapsed_time(ev1)
+            lat.append(g.latencies_ms())
+        g.check()
+        ms = tot / reps
+        per = np.median(np.stack(lat), axis=0)
+        rec = {"ms_per_batch": ms, "graph": mode == "batched", "components_per_s": n_tot / (ms * 1e-3),
+               "latency_ms_p50": float(np.percentile(per, 50)), "latency_ms_p99": float(np.percentile(per, 99)),
+               "latency_ms_max": float(per.max()), "replays": reps}
+        if mode == "batched":
+            worst = 0.0
+            for k, p in enumerate(probs):
+                nsd = p.geometry["sdx"] * p.geometry["sdy"]
+                ks = int(np.random.default_rng(3000 + k).integers(0, nsd))
+                pat = OG.subdomain_pattern(p.geometry, ks, p.obs_idx)
+                fac = OF.fit_subdomain(OF.anomalies(p.Xb)[1], pat, p.ridge)
+                X64 = np.asarray(p.Xb, np.float64)
+                Z = OA.solve_subdomain(fac, OA.innovations(X64, p.Y, p.obs_idx, pat), p.r_diag)
+                rows = pat.loc2glob[pat.interior]
+                ref = X64[rows] + Z[pat.interior]
+                xa = g.Xa[k][torch.as_tensor(rows, device="cuda")].double().mean(1).cpu().numpy()
+                worst = max(worst, float(np.linalg.norm(xa - ref.mean(1)) / np.linalg.norm(ref.mean(1))))
+            rec["rel_err_mean_vs_oracle_worst_instance"] = worst
+        out[mode] = rec
+        log(f"c5 {mode}: {ms:.2f} ms per batch, {n_tot / (ms * 1e-3):.4g} components/s, latency p50 "
+            f"{rec['latency_ms_p50']:.3f} ms p99 {rec['latency_ms_p99']:.3f} ms")
+        g.close()
+        for it in items:
+            it["plan"].close()
+        del g, items
+        torch.cuda.empty_cache()
+    out["speedup_vs_plain"] = out["plain"]["ms_per_batch"] / out["batched"]["ms_per_batch"]
+    return out
+
+
 def study(cycles: int) -> None:
     """RMSE of eq. (18) and time per assimilation cycle at the T-63 size against
     the ridge (at 24x12 sub-domains) and against the number of sub-domains Delta
@@ -122,7 +341,15 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-subdomains", type=int, default=14)
+    ap.add_argument("--cpu-subdomains", type=int, default=32)
+    ap.add_argument("--svd-steps", type=int, default=1,
+                    help="also time this many fit steps in the SVD mode (Section 5 route; 0: skip)")
+    ap.add_argument("--c5", action="store_true",
+                    help="also run the uneven batch of 64 instances in one HIP graph (p50/p99 latency)")
+    ap.add_argument("--c5-branches", type=int, default=4)
+    ap.add_argument("--c5-replays", type=int, default=10)
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the ring40 and grid96x48 lines (batched vs plain, error vs the whole oracle)")
     ap.add_argument("--adjoint-steps", type=int, default=3,
                     help="also time fit + analyze + enkfmc_analyze_backward this many times (0: skip)")
     ap.add_argument("--cycles", type=int, default=4,
@@ -136,6 +363,11 @@ def main():
         print("bench.py measures one GPU: the sub-domains of this workload would be sharded in latitude bands "
               "across GPUs, but the library has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    pool = None
+    if not args.no_cpu_baseline and not args.study:
+        pool, workers, affinity, barrier = start_cpu_pool()   # before this process touches the GPU
+        log(f"cpu baseline: {workers} oracle worker processes (affinity {affinity} cores)")
 
     import numpy as np
     import torch
@@ -161,26 +393,38 @@ def main():
     r = torch.as_tensor(prob.r_diag).cuda()
     plan.ensure_workspace()
     lam = prob.ridge
+    if pool is not None:
+        barrier.wait(timeout=300)   # the workers have built their copy of the workload and wait idle
 
-    def step(mode):
+    def step(mode, acc=None):
+        # a timed call reports the phases it ran: read them after each call
         plan.fit(Xb, lam, mode=mode)
-        return plan.analyze(Xb, Y, r)
+        if acc is not None:
+            for k, v in plan.timing().items():
+                acc[k] = acc.get(k, 0.0) + v
+        Xa_ = plan.analyze(Xb, Y, r)
+        if acc is not None:
+            for k, v in plan.timing().items():
+                acc[k] = acc.get(k, 0.0) + v
+        return Xa_
 
-    def timed(mode, steps, warmup):
+    def timed(mode, steps, warmup, phase_steps=3):
+        # the throughput is timed without per-kernel events; the phases come
+        # from a separate instrumented pass
         for _ in range(warmup):
             step(mode)
-        plan.set_timing(True)
-        acc = {}
         torch.cuda.synchronize()
         t = time.perf_counter()
         for i in range(steps):
             Xa = step(mode)
-            for k, v in plan.timing().items():
-                acc[k] = acc.get(k, 0.0) + v
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
+        plan.set_timing(True)
+        acc = {}
+        for i in range(phase_steps):
+            step(mode, acc)
         plan.set_timing(False)
-        return dt, {k: v / steps for k, v in acc.items()}, Xa
+        return dt, {k: v / phase_steps for k, v in acc.items()}, Xa
 
     log(f"warmup {args.warmup} + {args.steps} timed steps ({args.mode})")
     dt, phases, Xa = timed(args.mode, args.steps, args.warmup)
@@ -190,7 +434,7 @@ def main():
 
     plain = None
     if not args.no_plain and args.mode != "plain":
-        pdt, pph, _ = timed("plain", args.plain_steps, 1)
+        pdt, pph, _ = timed("plain", args.plain_steps, 1, phase_steps=1)
         plain = {"ms_per_step": pdt * 1e3, "value": prob.n / pdt, "phases_ms": pph}
         log(f"plain: {pdt * 1e3:.2f} ms/step; phases(ms) " + ", ".join(f"{k}={v:.3f}" for k, v in pph.items() if v > 0))
         Xa = step(args.mode)
@@ -269,43 +513,50 @@ def main():
                 "frac": achieved / PEAK_FP64, "traffic": None, "fit_phase": fit_all}
     Xa_h = Xa.cpu().numpy()
 
+    svd = None
+    if args.svd_steps > 0 and args.mode == "batched":
+        # the regressions by the SVD of their design matrices (Section 5),
+        # timed beside the Cholesky fit on the same inputs
+        plan.set_timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.svd_steps):
+            plan.fit(Xb, lam, mode="svd")
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t) / args.svd_steps
+        fit_svd_ms = plan.timing()["fit"]
+        plan.set_timing(False)
+        Xs = plan.analyze(Xb, Y, r)
+        d_svd = float(torch.max(torch.abs(Xs - Xa)) / torch.max(torch.abs(Xa)))
+        svd = {"ms_fit_call": ts * 1e3, "ms_fit_kernels": fit_svd_ms, "ms_fit_cholesky_batched": phases.get("fit"),
+               "max_rel_diff_Xa_vs_cholesky": d_svd,
+               "note": "enkfmc_fit in ENKFMC_FIT_SVD (one-sided Jacobi per regression, FP64) on the same inputs"}
+        log(f"svd fit: {ts * 1e3:.1f} ms per call (kernels {fit_svd_ms:.1f} ms) vs {phases.get('fit'):.1f} ms "
+            f"Cholesky; X_a differs by {d_svd:.2e}")
+        Xa = step(args.mode)
+        Xa_h = Xa.cpu().numpy()
+
+    small = None
+    if not args.no_small and args.mode == "batched":
+        small = {}
+        for name in ("ring40", "grid96x48"):
+            small[name] = small_config(name)
+            s_ = small[name]
+            log(f"{name}: batched {s_['batched']['ms_per_step']:.3f} ms, plain {s_['plain']['ms_per_step']:.3f} ms, "
+                f"rel err {s_['batched']['rel_err_mean_vs_oracle']:.2e} / {s_['plain']['rel_err_mean_vs_oracle']:.2e}")
+
+    c5 = None
+    if args.c5 and args.mode == "batched":
+        c5 = c5_bench(args.c5_replays, args.c5_branches)
+
     cpu = None
     rel = None
-    if not args.no_cpu_baseline:
-        from threadpoolctl import threadpool_limits
-
-        from oracle import analysis as OA
-        from oracle import fit as OF
-        from oracle import geometry as OG
-        g = np.random.default_rng(0)
-        ks = [0, 24 * 6 + 11] + sorted(g.choice(np.arange(1, 287), args.cpu_subdomains - 2, replace=False).tolist())
-        mean, U = OF.anomalies(prob.Xb)
-        X64 = np.asarray(prob.Xb, np.float64)
-        diff2 = ref2 = 0.0
-        comps = 0
-        maxabs = 0.0
-        tcpu = 0.0
-        with threadpool_limits(1):
-            for k in ks:
-                pat = OG.subdomain_pattern(prob.geometry, k, prob.obs_idx)
-                t = time.perf_counter()
-                fac = OF.fit_subdomain(U, pat, lam)
-                innov = OA.innovations(X64, prob.Y, prob.obs_idx, pat)
-                Z = OA.solve_subdomain(fac, innov, prob.r_diag)
-                tcpu += time.perf_counter() - t
-                rows = pat.loc2glob[pat.interior]
-                xa_ref = X64[rows] + Z[pat.interior]
-                comps += rows.size
-                diff2 += float(np.sum((Xa_h[rows].mean(1) - xa_ref.mean(1)) ** 2))
-                ref2 += float(np.sum(xa_ref.mean(1) ** 2))
-                maxabs = max(maxabs, float(np.max(np.abs(Xa_h[rows] - xa_ref))))
-                log(f"oracle sub-domain {k}: {tcpu:.1f}s so far")
-        rel = float(np.sqrt(diff2 / ref2))
-        cpu = {"value": comps / tcpu, "unit": "components/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(ks)} of 288 sub-domains (fit of all their {len(ks)}x7424 local rows + local "
-                         f"solves), {comps} interior components, {tcpu:.1f}s, BLAS limited to 1 thread"}
-        log(f"oracle: {cpu['value']:.4g} components/s; GPU vs oracle on those sub-domains: mean rel err {rel:.2e}, "
-            f"max abs {maxabs:.2e}")
+    if pool is not None:
+        cpu, rel, maxabs = cpu_baseline(pool, workers, affinity, prob, Xa_h, args.cpu_subdomains)
+        pool.close()
+        pool.join()
+        log(f"oracle: {cpu['value']:.4g} components/s on {cpu['cores']} cores; GPU vs oracle on those sub-domains: "
+            f"mean rel err {rel:.2e}, max abs {maxabs:.2e}")
 
     out = {
         "metric": METRIC, "value": value, "unit": "components/s", "n_gpus": 1, "steps": args.steps,
@@ -322,6 +573,9 @@ def main():
         "cpu_baseline": cpu,
         "adjoint": adjoint,
         "cycles": cyc,
+        "svd_fit": svd,
+        "small_workloads": small,
+        "uneven_batch_graph": c5,
     }
     print(json.dumps(out), flush=True)
     if args.copy_probe_mib > 0:

@@ -72,7 +72,10 @@ typedef enum {
 
 /* How enkfmc_analyze solves the local systems (same result within rounding). */
 typedef enum {
-  ENKFMC_SOLVE_DUAL = 0   /* direct: dual form eqs. (12)-(13) per variable block  */
+  ENKFMC_SOLVE_DUAL = 0,  /* direct: dual form eqs. (12)-(13) per variable block  */
+  ENKFMC_SOLVE_PCG = 1    /* iterative: conjugate gradients on the primal eq. (11)
+                             per (block, member), preconditioned by B^ = T^-1 D T^-T
+                             (eq. 8), FP64 with residual refinement */
 } enkfmc_solver;
 
 typedef struct {
@@ -145,7 +148,16 @@ enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t 
  * Xb: dev (n x N, dtype, ld); Y: dev (m x N) float64 perturbed observations;
  * r_diag: dev (m) float64 > 0; Xa: dev (n x N) contiguous, element type
  * out_dtype.  The local increments of all rows stay in the workspace for
- * enkfmc_analyze_backward.  Errors: EINVAL, ESTATE, ENOTSPD, EHIP. */
+ * enkfmc_analyze_backward.  solver: enkfmc_solver.  ENKFMC_SOLVE_PCG iterates
+ * (Section 2.3 after eq. 13: the primal system by an iterative solver) until
+ * every (block, member) column's residual, in the norm of the
+ * preconditioner, is below rtol times its initial value, then recomputes
+ * the residual from the solution in FP64 and restarts where it is still
+ * above (enkfmc_set_pcg sets rtol and the iteration limit); it needs
+ * synchronous calls (not enkfmc_set_async).
+ * Errors: EINVAL, ESTATE, ENOTSPD, EHIP, ENOCONV (PCG: some column still
+ * above rtol after maxit iterations; X_a then holds the last iterate and
+ * the reverse pass is refused). */
 enkfmc_status enkfmc_analyze(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t ld, const double *Y,
                              const double *r_diag, void *Xa, int32_t out_dtype, int32_t solver, void *stream);
 
@@ -237,6 +249,17 @@ enkfmc_status enkfmc_get_factors(enkfmc_plan *p, int32_t k, double *tval, double
  * halo rows included. */
 enkfmc_status enkfmc_get_increment(enkfmc_plan *p, int32_t k, double *Z, void *stream);
 
+/* Limits of ENKFMC_SOLVE_PCG: at most maxit >= 1 iterations (default 2000),
+ * relative tolerance 0 < rtol < 1 on the preconditioned residual norm
+ * (default 1e-12).  Iterations run in HIP graphs of 8, so the count is a
+ * multiple of 8 (a column that converges stops changing).
+ * enkfmc_get_pcg_stats reports the last PCG analysis: iterations run,
+ * the largest per-column count, the restarts after refinement and the
+ * largest final relative residual over the columns. */
+enkfmc_status enkfmc_set_pcg(enkfmc_plan *p, int32_t maxit, double rtol);
+enkfmc_status enkfmc_get_pcg_stats(enkfmc_plan *p, int32_t *iterations, int32_t *max_column_iterations,
+                                   int32_t *refinements, double *max_rel_residual, void *stream);
+
 /* Asynchronous mode of a plan (enable != 0), for running many plans
  * concurrently and for capturing calls into a HIP graph: enkfmc_fit,
  * enkfmc_analyze and enkfmc_analyze_backward then only enqueue their kernels
@@ -280,7 +303,8 @@ enum {
   ENKFMC_PH_ADJ_REGRESS = 14, /* adjoint of the regressions (within BACKWARD)      */
   ENKFMC_PH_ADJ_GATHER = 15, /* adjoint: halo gathers, dlog r, dlam (within BACKWARD) */
   ENKFMC_PH_FIT_FALLBACK = 16, /* batched fit: rows of the plain bucket alone, within FIT */
-  ENKFMC_PH_COUNT = 17
+  ENKFMC_PH_PCG = 17,      /* ENKFMC_SOLVE_PCG: the whole iteration                 */
+  ENKFMC_PH_COUNT = 18
 };
 enkfmc_status enkfmc_set_timing(enkfmc_plan *p, int32_t enable);
 enkfmc_status enkfmc_get_timing(const enkfmc_plan *p, int32_t phase, double *ms);

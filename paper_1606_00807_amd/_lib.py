@@ -18,10 +18,10 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "ENONPOS_D", -4: "ENOCONV", 
           -7: "ESTATE", -8: "EUNSUPPORTED"}
 F32, F64 = 0, 1
 FIT_PLAIN, FIT_BATCHED, FIT_SVD = 0, 1, 2
-SOLVE_DUAL = 0
+SOLVE_DUAL, SOLVE_PCG = 0, 1
 PHASES = ["anomaly", "fit", "dual_F", "dual_S", "dual_chol", "dual_Q", "dual_G", "sweep", "mapback", "backward",
           "tiles", "fit_kform",
-          "adj_solve", "adj_factor", "adj_regress", "adj_gather", "fit_fallback"]
+          "adj_solve", "adj_factor", "adj_regress", "adj_gather", "fit_fallback", "pcg"]
 
 
 class Geometry(ctypes.Structure):
@@ -68,6 +68,9 @@ SIGNATURES = {
     "enkfmc_get_increment": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_void_p]),
     "enkfmc_set_timing": (c_int32, [c_void_p, c_int32]),
     "enkfmc_set_async": (c_int32, [c_void_p, c_int32]),
+    "enkfmc_set_pcg": (c_int32, [c_void_p, c_int32, c_double]),
+    "enkfmc_get_pcg_stats": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                                       POINTER(c_double), c_void_p]),
     "enkfmc_check_status": (c_int32, [c_void_p, c_void_p]),
     "enkfmc_timestamp": (c_int32, [c_void_p, c_void_p]),
     "enkfmc_wall_clock_hz": (c_int32, [POINTER(c_int64)]),

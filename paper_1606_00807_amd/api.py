@@ -9,9 +9,10 @@ from typing import Dict, Optional, Tuple
 import numpy as np
 
 from . import _lib
-from ._lib import EnkfmcError, F32, F64, FIT_BATCHED, FIT_PLAIN, FIT_SVD, SOLVE_DUAL, check  # noqa: F401
+from ._lib import EnkfmcError, F32, F64, FIT_BATCHED, FIT_PLAIN, FIT_SVD, SOLVE_DUAL, SOLVE_PCG, check  # noqa: F401
 
 _MODES = {"plain": FIT_PLAIN, "batched": FIT_BATCHED, "svd": FIT_SVD}
+_SOLVERS = {"dual": SOLVE_DUAL, "pcg": SOLVE_PCG}
 
 
 def _ptr(a: np.ndarray, ctype):
@@ -184,8 +185,24 @@ class Plan:
         self._token = getattr(self, "_token", 0) + 1
         check(self.lib.enkfmc_fit(self._h, p, dt, ld, float(ridge), _MODES[mode], self._stream()))
 
-    def analyze(self, Xb, Y, r_diag, out_dtype=None):
-        """Local analyses + merge (eq. 11/14, Alg. 2-3).  Returns X_a (n, N)."""
+    def set_pcg(self, maxit: int = 2000, rtol: float = 1e-12) -> None:
+        """Iteration limit and relative tolerance of solver="pcg"."""
+        check(self.lib.enkfmc_set_pcg(self._h, int(maxit), float(rtol)))
+
+    def pcg_stats(self) -> Dict:
+        """Iterations, largest per-column count, refinement restarts and the
+        largest final relative residual of the last PCG analysis."""
+        it, mc, rf = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        rr = ctypes.c_double()
+        check(self.lib.enkfmc_get_pcg_stats(self._h, ctypes.byref(it), ctypes.byref(mc), ctypes.byref(rf),
+                                            ctypes.byref(rr), self._stream()))
+        return {"iterations": it.value, "max_column_iterations": mc.value, "refinements": rf.value,
+                "max_rel_residual": rr.value}
+
+    def analyze(self, Xb, Y, r_diag, out_dtype=None, solver: str = "dual"):
+        """Local analyses + merge (eq. 11/14, Alg. 2-3).  Returns X_a (n, N).
+        solver: "dual" (eqs. 12-13, direct) or "pcg" (primal eq. 11 by
+        B^-preconditioned conjugate gradients)."""
         import torch
         self._check_xb(Xb)
         Y = self._dev64(Y, (self.m, self.N), "Y")
@@ -197,7 +214,8 @@ class Plan:
         self._token = getattr(self, "_token", 0) + 1
         check(self.lib.enkfmc_analyze(self._h, p, dt, ld, ctypes.c_void_p(Y.data_ptr()),
                                       ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(Xa.data_ptr()),
-                                      F32 if out_dtype == torch.float32 else F64, SOLVE_DUAL, self._stream()))
+                                      F32 if out_dtype == torch.float32 else F64, _SOLVERS[solver],
+                                      self._stream()))
         # the reverse pass reads the same device copies of Y and r_diag
         self._analysis_inputs = (Y, r)
         return Xa

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libenkfmc.so")
 SOURCES = ["plan.cpp", "api.hip", "fit_plain.hip", "fit_batched.hip", "fit_svd.hip", "analysis.hip",
-           "backward.hip", "cycling.hip"]
+           "pcg.hip", "backward.hip", "cycling.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=fast",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -24,18 +24,7 @@
 
 namespace enkfmc {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
-
-__device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-
-// Orders this wavefront's LDS accesses: LDS executes one wavefront's
-// operations in issue order, so this only keeps the compiler from moving
-// memory operations across it.
-__device__ inline void wave_lds_sync() {
-  __asm__ __volatile__("" ::: "memory");
-  __builtin_amdgcn_wave_barrier();
-}
 
 // Dense tiles T_RC (row-major) of row tile R, and the inverse of T_RR.
 // One wavefront per (block, row tile).  The CSR entries of the tile's 16 rows
@@ -739,11 +728,10 @@ hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const
   return hipGetLastError();
 }
 
-template <typename TX>
-static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int64_t ld, const double *Y,
-                                 const double *r_diag, void *Xa, int32_t out_dtype, hipStream_t s) {
+// F = T^-T H^T, S = R + F^T D F and the Cholesky factor of S of every block
+// (the parts of the dual form that do not depend on the innovations).
+hipError_t launch_dual_factor(enkfmc_plan *p, const Dev &d, const double *r_diag, hipStream_t s) {
   const unsigned nb = (unsigned)p->blocks.size();
-  const int N = p->N;
   const unsigned oc = (unsigned)((p->max_bm + 15) / 16);
   if (p->max_bm > 0) {
     phase_begin(p, ENKFMC_PH_DUAL_F, s);
@@ -766,13 +754,15 @@ static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
     else
       hipLaunchKernelGGL(k_dual_chol, dim3(nb), dim3(256), 0, s, d.blocks, d.S, d.status);
     phase_end(p, ENKFMC_PH_DUAL_CHOL, s);
-    phase_begin(p, ENKFMC_PH_DUAL_Q, s);
-    hipLaunchKernelGGL(k_dual_Q<TX>, dim3(nb, (N + 63) / 64), dim3(64), 0, s, d.blocks, d.bobs_o, d.bobs_row,
-                       d.fit_glob, d.S, Y, Xb, ld, N, d.Q);
-    phase_end(p, ENKFMC_PH_DUAL_Q, s);
   }
-  hipError_t e = launch_fwd_sweep(p, d, d.Q, nullptr, d.Z, s);
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// X_a = X_b + Z on interior rows.
+template <typename TX>
+static hipError_t mapback_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int64_t ld, void *Xa, int32_t out_dtype,
+                                hipStream_t s) {
+  const int N = p->N;
   const int64_t tot = p->n * N;
   const dim3 g((unsigned)((tot + 255) / 256));
   phase_begin(p, ENKFMC_PH_MAPBACK, s);
@@ -783,6 +773,30 @@ static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
                        (double *)Xa);
   phase_end(p, ENKFMC_PH_MAPBACK, s);
   return hipGetLastError();
+}
+
+hipError_t launch_mapback(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, void *Xa,
+                          int32_t out_dtype, hipStream_t s) {
+  if (dtype == ENKFMC_F32) return mapback_typed(p, d, (const float *)Xb, ld, Xa, out_dtype, s);
+  return mapback_typed(p, d, (const double *)Xb, ld, Xa, out_dtype, s);
+}
+
+template <typename TX>
+static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int64_t ld, const double *Y,
+                                 const double *r_diag, void *Xa, int32_t out_dtype, hipStream_t s) {
+  const unsigned nb = (unsigned)p->blocks.size();
+  const int N = p->N;
+  hipError_t e = launch_dual_factor(p, d, r_diag, s);
+  if (e != hipSuccess) return e;
+  if (p->max_bm > 0) {
+    phase_begin(p, ENKFMC_PH_DUAL_Q, s);
+    hipLaunchKernelGGL(k_dual_Q<TX>, dim3(nb, (N + 63) / 64), dim3(64), 0, s, d.blocks, d.bobs_o, d.bobs_row,
+                       d.fit_glob, d.S, Y, Xb, ld, N, d.Q);
+    phase_end(p, ENKFMC_PH_DUAL_Q, s);
+  }
+  e = launch_fwd_sweep(p, d, d.Q, nullptr, d.Z, s);
+  if (e != hipSuccess) return e;
+  return mapback_typed(p, d, Xb, ld, Xa, out_dtype, s);
 }
 
 

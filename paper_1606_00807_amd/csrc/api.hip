@@ -225,16 +225,28 @@ enkfmc_status enkfmc_analyze(enkfmc_plan *p, const void *Xb, int32_t dtype, int6
   if (dtype != ENKFMC_F32 && dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "analyze: bad dtype");
   if (out_dtype != ENKFMC_F32 && out_dtype != ENKFMC_F64) return fail(ENKFMC_EINVAL, "analyze: bad out_dtype");
   if (ld < p->N) return fail(ENKFMC_EINVAL, "analyze: ld < N");
-  if (solver != ENKFMC_SOLVE_DUAL) return fail(ENKFMC_EINVAL, "analyze: unknown solver");
+  if (solver != ENKFMC_SOLVE_DUAL && solver != ENKFMC_SOLVE_PCG) return fail(ENKFMC_EINVAL, "analyze: unknown solver");
+  if (solver == ENKFMC_SOLVE_PCG && p->async)
+    return fail(ENKFMC_EINVAL, "analyze: the PCG solver reads its convergence on the host; not in asynchronous mode");
   if (!p->fitted || p->fit_xb != Xb) return fail(ENKFMC_ESTATE, "analyze: needs the preceding fit on the same X_b");
   hipStream_t s = (hipStream_t)stream;
   enkfmc_status st = begin(p, s, "analyze");
   if (st != ENKFMC_OK) return st;
   p->analyzed = 0;
   const Dev d = make_dev(p);
-  HIPCHK(launch_analysis_dual(p, d, Xb, dtype, ld, Y, r_diag, Xa, out_dtype, s), "analyze: launch");
+  int32_t converged = 1;
+  if (solver == ENKFMC_SOLVE_PCG) {
+    HIPCHK(launch_analysis_pcg(p, d, Xb, dtype, ld, Y, r_diag, s, &converged), "analyze: pcg");
+    HIPCHK(launch_mapback(p, d, Xb, dtype, ld, Xa, out_dtype, s), "analyze: map back");
+  } else {
+    HIPCHK(launch_analysis_dual(p, d, Xb, dtype, ld, Y, r_diag, Xa, out_dtype, s), "analyze: launch");
+  }
   st = finish(p, s, "analyze");
   if (st != ENKFMC_OK) return st;
+  if (!converged)
+    return fail(ENKFMC_ENOCONV, "analyze: PCG did not reach rtol within " + std::to_string(p->pcg_maxit) +
+                                    " iterations");
+  p->an_solver = solver;
   p->analyzed = 1;
   p->an_y = Y;
   p->an_r = r_diag;
@@ -255,6 +267,9 @@ enkfmc_status enkfmc_analyze_backward(enkfmc_plan *p, const void *Xb, int32_t dt
   enkfmc_status st = begin(p, s, "analyze_backward");
   if (st != ENKFMC_OK) return st;
   const Dev d = make_dev(p);
+  // the reverse pass solves with the dual form: after a PCG analysis its
+  // factors (F, S and the Cholesky factor of S) are not there yet
+  if (p->an_solver == ENKFMC_SOLVE_PCG) HIPCHK(launch_dual_factor(p, d, r_diag, s), "analyze_backward: dual factors");
   HIPCHK(launch_backward(p, d, Xb, dtype, ld, Y, r_diag, p->fit_ridge, dXa, dXb, dlogR, dridge, s),
          "analyze_backward: launch");
   return finish(p, s, "analyze_backward");
@@ -382,6 +397,24 @@ enkfmc_status enkfmc_get_increment(enkfmc_plan *p, int32_t k, double *Z, void *s
   return ENKFMC_OK;
 }
 
+enkfmc_status enkfmc_set_pcg(enkfmc_plan *p, int32_t maxit, double rtol) {
+  if (!p || maxit < 1 || !(rtol > 0.0 && rtol < 1.0)) return fail(ENKFMC_EINVAL, "set_pcg: need maxit >= 1, 0 < rtol < 1");
+  p->pcg_maxit = maxit;
+  p->pcg_rtol = rtol;
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_get_pcg_stats(enkfmc_plan *p, int32_t *iterations, int32_t *max_column_iterations,
+                                   int32_t *refinements, double *max_rel_residual, void *stream) {
+  if (!p || !iterations || !max_column_iterations || !refinements || !max_rel_residual)
+    return fail(ENKFMC_EINVAL, "get_pcg_stats: NULL argument");
+  if (!p->ws) return fail(ENKFMC_ESTATE, "get_pcg_stats: no workspace");
+  *iterations = p->pcg_iters;
+  *refinements = p->pcg_refinements;
+  HIPCHK(pcg_column_stats(p, (hipStream_t)stream, max_column_iterations, max_rel_residual), "get_pcg_stats");
+  return ENKFMC_OK;
+}
+
 enkfmc_status enkfmc_set_async(enkfmc_plan *p, int32_t enable) {
   if (!p) return fail(ENKFMC_EINVAL, "set_async: NULL plan");
   p->async = enable ? 1 : 0;
@@ -458,6 +491,8 @@ void enkfmc_plan_destroy(enkfmc_plan *p) {
   if (!p) return;
   for (int i = 0; i < 64; ++i)
     if (p->ev[i]) hipEventDestroy((hipEvent_t)p->ev[i]);
+  if (p->pcg_exec) hipGraphExecDestroy((hipGraphExec_t)p->pcg_exec);
+  if (p->pcg_cap_stream) hipStreamDestroy((hipStream_t)p->pcg_cap_stream);
   delete p;
 }
 

@@ -31,17 +31,6 @@
 
 namespace enkfmc {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-__device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-
-// LDS written by some lanes of a wavefront and read by others: a wavefront
-// executes its LDS instructions in order, so only the compiler must not move
-// them across this point.
-__device__ inline void wave_lds_sync() {
-  __asm__ __volatile__("" ::: "memory");
-  __builtin_amdgcn_wave_barrier();
-}
 
 // Zbar of fit row f: the output gradient of its component if f is the row that
 // maps back onto it, else 0.
@@ -155,11 +144,17 @@ __global__ __launch_bounds__(64) void k_adj_solve_S(const Block *__restrict__ bl
 }
 
 // Dbar and betabar by 16-row tiles of T.  One wavefront per (block, row tile
-// R): TZ_R = Z_R + sum_C T_RC Z_C and TW_R likewise (C over the pattern's
-// tiles of R, the strictly lower T_RR included) by MFMA, kept in LDS scaled by
-// 1/d; Dbar_i = (TW)_i . (TZ)_i / d_i^2; then per tile (R, C) of the pattern
-// the 16 x 16 products (TZ_R/d) W_C^T + (TW_R/d) Z_C^T, of which the entries in
-// the pattern of T are betabar, written in CSR order.  LDS: 2 x 16 x (N + 1) + 16 x 17 doubles.
+// R).  First TZ_R = Z_R + sum_C T_RC Z_C and TW_R likewise (C over the
+// pattern's tiles of R, the strictly lower T_RR included), accumulated
+// transposed: with the operands of each v_mfma_f64_16x16x4 swapped, member
+// tile g's accumulator holds (TZ_R)^T, so lane (q, c) keeps rows c of TZ_R and
+// TW_R at members 16g + 4r + q -- exactly the A operands the 16 x 16 products
+// below need, so they stay in registers (scaled by 1/d_c).
+// Dbar_i = (TW)_i . (TZ)_i / d_i^2 is a sum over each lane's members and then
+// over the four rows of 16 lanes.  Then per tile (R, C) of the pattern the
+// products (TZ_R/d) W_C^T + (TW_R/d) Z_C^T, of which the entries in the
+// pattern of T are betabar, written in CSR order through a 16 x 17 LDS tile.
+template <int G>
 __global__ __launch_bounds__(64) void k_adj_factor_tiles(const Block *__restrict__ blocks,
                                                          const int64_t *__restrict__ row_ptr,
                                                          const int32_t *__restrict__ col,
@@ -172,85 +167,80 @@ __global__ __launch_bounds__(64) void k_adj_factor_tiles(const Block *__restrict
                                                          const double *__restrict__ dvec, const double *__restrict__ Z,
                                                          const double *__restrict__ W, int N, int ntile,
                                                          double *__restrict__ dbar, double *__restrict__ bbar) {
-  extern __shared__ double sm[];
+  __shared__ double sout[16 * 17];
   int bi, R;
   block_tile(ntile, bi, R);
   const Block B = blocks[bi];
   if (R >= B.nrt) return;
   const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
-  const int ldn = N + 1;
-  double *sTZ = sm, *sTW = sm + 16 * ldn, *sout = sm + 32 * ldn;
   const int64_t rt = B.rt0 + R;
   const int64_t t0 = rt_ptr[rt];
   const int nt = (int)(rt_ptr[rt + 1] - t0);
   const double *Zb = Z + B.row0 * N, *Wb = W + B.row0 * N;
-  double dinv[4], dpart[4];
+  const int rowc = 16 * R + c;                   // the row this lane's accumulators hold
+  const double dinv = rowc < B.n ? 1.0 / dvec[B.row0 + rowc] : 0.0;
+  d4 az[G], aw[G];
+  // identity part: (Z_R)^T at lane (q, c), register r: Z[16R + c][16g + 4r + q]
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = 16 * R + 4 * r + q;
-    dinv[r] = row < B.n ? 1.0 / dvec[B.row0 + row] : 0.0;
-    dpart[r] = 0.0;
-  }
-  for (int cc = 0; 16 * cc < N; ++cc) {
-    const int colj = 16 * cc + c;
-    const bool colok = colj < N;
-    d4 az, aw;
+  for (int g = 0; g < G; ++g) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 16 * R + 4 * r + q;
-      const bool in = row < B.n && colok;
-      az[r] = in ? Zb[(int64_t)row * N + colj] : 0.0;
-      aw[r] = in ? Wb[(int64_t)row * N + colj] : 0.0;
+      const int m = 16 * g + 4 * r + q;
+      const bool in = rowc < B.n && m < N;
+      az[g][r] = in ? Zb[(int64_t)rowc * N + m] : 0.0;
+      aw[g][r] = in ? Wb[(int64_t)rowc * N + m] : 0.0;
     }
-#pragma unroll 2
-    for (int t = 0; t <= nt; ++t) {            // t == nt: the diagonal tile
-      const int C = t < nt ? rt_col[t0 + t] : R;
-      const double *Tt = t < nt ? tiles + (int64_t)rt_slot[t0 + t] * 256 : tdiag + rt * 256;
+  }
+  for (int t = 0; t <= nt; ++t) {                // t == nt: the diagonal tile
+    const int C = t < nt ? rt_col[t0 + t] : R;
+    const double *Tt = t < nt ? tiles + (int64_t)rt_slot[t0 + t] * 256 : tdiag + rt * 256;
+    double tb[4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) tb[kc] = Tt[c * 16 + 4 * kc + q];   // B operand: T_RC^T[4kc + q][c]
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int m = 16 * g + c;
+      const bool min = m < N;
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc) {
-        const double a = Tt[c * 16 + 4 * kc + q];
-        const int zr = 16 * C + 4 * kc + q;
-        const bool in = zr < B.n && colok;
-        az = mfma64(a, in ? Zb[(int64_t)zr * N + colj] : 0.0, az);
-        aw = mfma64(a, in ? Wb[(int64_t)zr * N + colj] : 0.0, aw);
+        const int zr = 16 * C + 4 * kc + q;      // A operand: Z_C^T[m][4kc + q]
+        const bool in = zr < B.n && min;
+        az[g] = mfma64(in ? Zb[(int64_t)zr * N + m] : 0.0, tb[kc], az[g]);
+        aw[g] = mfma64(in ? Wb[(int64_t)zr * N + m] : 0.0, tb[kc], aw[g]);
       }
     }
+  }
+  double dp = 0.0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      dpart[r] = fma(az[r], aw[r], dpart[r]);
-      if (colok) {
-        sTZ[(4 * r + q) * ldn + colj] = az[r] * dinv[r];
-        sTW[(4 * r + q) * ldn + colj] = aw[r] * dinv[r];
-      }
+      dp = fma(az[g][r], aw[g][r], dp);
+      az[g][r] *= dinv;
+      aw[g][r] *= dinv;
     }
   }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    double v = dpart[r];
-    v += __shfl_xor(v, 8, 16);
-    v += __shfl_xor(v, 4, 16);
-    v += __shfl_xor(v, 2, 16);
-    v += __shfl_xor(v, 1, 16);
-    const int row = 16 * R + 4 * r + q;
-    if (c == 0 && row < B.n) dbar[B.row0 + row] = v * dinv[r] * dinv[r];
-  }
-  wave_lds_sync();
+  dp += __shfl_xor(dp, 16, 64);
+  dp += __shfl_xor(dp, 32, 64);
+  if (q == 0 && rowc < B.n) dbar[B.row0 + rowc] = dp * dinv * dinv;
   for (int t = 0; t <= nt; ++t) {
     const int C = t < nt ? rt_col[t0 + t] : R;
-    const int jr = 16 * C + c;                 // row of W_C, Z_C for the B operand
+    const int jr = 16 * C + c;                   // row of W_C, Z_C for the B operand
     const bool jin = jr < B.n;
-    d4 o = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 5
-    for (int ks = 0; 4 * ks < N; ++ks) {
-      const int k = 4 * ks + q;
-      const bool kin = k < N;
-      const double a1 = kin ? sTZ[c * ldn + k] : 0.0;
-      const double a2 = kin ? sTW[c * ldn + k] : 0.0;
-      const double bw = (jin && kin) ? Wb[(int64_t)jr * N + k] : 0.0;
-      const double bz = (jin && kin) ? Zb[(int64_t)jr * N + k] : 0.0;
-      o = mfma64(a1, bw, o);
-      o = mfma64(a2, bz, o);
+    d4 o1 = d4{0.0, 0.0, 0.0, 0.0}, o2 = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * g + 4 * r + q;        // k-step 4g + r: members 16g + 4r + q
+        const bool in = jin && k < N;
+        const double bw = in ? Wb[(int64_t)jr * N + k] : 0.0;
+        const double bz = in ? Zb[(int64_t)jr * N + k] : 0.0;
+        o1 = mfma64(az[g][r], bw, o1);
+        o2 = mfma64(aw[g][r], bz, o2);
+      }
     }
+    const d4 o = o1 + o2;
 #pragma unroll
     for (int r = 0; r < 4; ++r) sout[(4 * r + q) * 17 + c] = o[r];
     wave_lds_sync();
@@ -664,13 +654,22 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   phase_end(p, ENKFMC_PH_ADJ_SOLVE, s);
   phase_begin(p, ENKFMC_PH_ADJ_FACTOR, s);
   {
-    const size_t lds = (size_t)(32 * (N + 1) + 16 * 17) * 8;
-    e = hipFuncSetAttribute((const void *)k_adj_factor_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
     const int mt = max_block_tiles(p);
-    hipLaunchKernelGGL(k_adj_factor_tiles, dim3(nb * (unsigned)mt), dim3(64), lds, s, d.blocks, d.row_ptr, d.col,
-                       d.rt_ptr, d.rt_col, d.rt_slot, d.tile_eoff, d.tiles, d.tdiag, d.dvec, d.Z, d.W, N, mt, d.dbar,
-                       d.aux3);
+#define ADJ_FACTOR(G)                                                                                           \
+  hipLaunchKernelGGL(k_adj_factor_tiles<G>, dim3(nb * (unsigned)mt), dim3(64), 0, s, d.blocks, d.row_ptr, d.col, \
+                     d.rt_ptr, d.rt_col, d.rt_slot, d.tile_eoff, d.tiles, d.tdiag, d.dvec, d.Z, d.W, N, mt, d.dbar, \
+                     d.aux3)
+    switch ((N + 15) / 16) {   // member tiles kept in registers (N <= 128)
+      case 1: ADJ_FACTOR(1); break;
+      case 2: ADJ_FACTOR(2); break;
+      case 3: ADJ_FACTOR(3); break;
+      case 4: ADJ_FACTOR(4); break;
+      case 5: ADJ_FACTOR(5); break;
+      case 6: ADJ_FACTOR(6); break;
+      case 7: ADJ_FACTOR(7); break;
+      default: ADJ_FACTOR(8); break;
+    }
+#undef ADJ_FACTOR
   }
   phase_end(p, ENKFMC_PH_ADJ_FACTOR, s);
   phase_begin(p, ENKFMC_PH_ADJ_REGRESS, s);

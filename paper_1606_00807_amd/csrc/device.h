@@ -79,6 +79,22 @@ inline Dev make_dev(enkfmc_plan *p) {
   return d;
 }
 
+// A v_mfma_f64_16x16x4 accumulator (four doubles per lane).  Lane l = 16q + c
+// holds element (4r + q, c) in register r; the A operand of a product is
+// A[c][q] at lane (q, c), the B operand B[q][c].
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// Orders one wavefront's LDS accesses where lanes exchange values through
+// LDS: a wavefront executes its LDS instructions in issue order, so a read
+// issued after a write sees it; this only keeps the compiler from moving
+// memory operations across this point.
+__device__ inline void wave_lds_sync() {
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // First error wins; status[1] records where it happened.
 // MI355X dispatches the workgroups of a launch to its 8 XCDs in turn
 // (workgroup b to XCD b mod 8), and each XCD has an L2 of its own.  This maps
@@ -203,6 +219,12 @@ hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s);
 int max_block_tiles(const enkfmc_plan *p);
 hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const double *V, double *out,
                             hipStream_t s);
+hipError_t launch_analysis_pcg(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld,
+                               const double *Y, const double *r_diag, hipStream_t s, int32_t *converged);
+hipError_t pcg_column_stats(enkfmc_plan *p, hipStream_t s, int32_t *max_iter, double *max_rel);
+hipError_t launch_dual_factor(enkfmc_plan *p, const Dev &d, const double *r_diag, hipStream_t s);
+hipError_t launch_mapback(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, void *Xa,
+                          int32_t out_dtype, hipStream_t s);
 hipError_t launch_analysis_dual(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld,
                                 const double *Y, const double *r_diag, void *Xa, int32_t out_dtype, hipStream_t s);
 hipError_t launch_adj_regress_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);

@@ -44,8 +44,6 @@
 
 namespace enkfmc {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
 constexpr int kMaxT = 8;          // largest tile count handled here (m <= 128, N <= 128)
 constexpr int kMaxP = 192;        // largest predecessor count handled here
 
@@ -56,22 +54,11 @@ struct WaveLds {                  // wavefront-private LDS (doubles unless noted
   double tile[kMaxP + 16 * kMaxT]; // scratch: bordering row, adjoint vectors
 };
 
-__device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-
 __device__ inline double readlane_d(double v, int lane) {
   const long long bits = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), lane);
   const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Orders this wavefront's LDS accesses (lanes exchange values through LDS).
-// LDS executes one wavefront's operations in issue order and returns them in
-// order, so a read issued after a write sees it; this barrier only keeps the
-// compiler from reordering memory operations across this point.
-__device__ inline void wave_lds_sync() {
-  __asm__ __volatile__("" ::: "memory");
-  __builtin_amdgcn_wave_barrier();
 }
 
 // 1/sqrt(x) for x > 0: hardware estimate refined by one Newton step.  On

@@ -353,6 +353,7 @@ void compute_layout(enkfmc_plan *p) {
   L.tinv = take((size_t)p->n_rt * 256 * 8);
   L.tdiag = take((size_t)p->n_rt * 256 * 8);
   L.ubar = take(nf * N * 8);
+  L.pcg = take((size_t)5 * nb * N * 8 + 64);   // per (block, member) scalars of the PCG + its counter
   L.status = take(64);
   L.total = off;
 }

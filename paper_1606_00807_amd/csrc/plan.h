@@ -51,7 +51,7 @@ struct Layout {
   size_t blocks, fit_glob, fit_blk, fit_rows, row_ptr, col, csc_ptr, csc_row, csc_nz, interior_src, bobs_o, bobs_row;
   size_t g2f_ptr, g2f, o2b_ptr, o2b, bobs_fit, ot_jmax;
   size_t rt_ptr, rt_col, rt_slot, ct_ptr, ct_row, ct_slot, tile_eoff;
-  size_t tval, dvec, mean, U, Z, F, S, Q, P, W, aux1, aux2, aux3, dbar, red, tiles, tinv, tdiag, ubar, status;
+  size_t tval, dvec, mean, U, Z, F, S, Q, P, W, aux1, aux2, aux3, dbar, red, tiles, tinv, tdiag, ubar, pcg, status;
   size_t total;
 };
 
@@ -110,6 +110,15 @@ struct enkfmc_plan {
   // optional per-phase timing with HIP events on the call's stream
   int32_t timing = 0;
   int32_t async = 0;               // calls neither clear nor read the status word (enkfmc_set_async)
+  int32_t an_solver = 0;           // enkfmc_solver of the last analysis
+  // preconditioned CG of the local systems (ENKFMC_SOLVE_PCG)
+  int32_t pcg_maxit = 2000;
+  double pcg_rtol = 1e-12;
+  int32_t pcg_iters = 0, pcg_refinements = 0;
+  void *pcg_exec = nullptr;        // hipGraphExec_t of a run of iterations
+  void *pcg_cap_stream = nullptr;  // stream the graph was captured on
+  double pcg_graph_tol2 = -1.0;
+  const char *pcg_graph_ws = nullptr;
   void *ev[64] = {};
   uint64_t recorded = 0;
   double phase_ms[32] = {};
