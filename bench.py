@@ -333,6 +333,8 @@ def study(cycles: int) -> None:
 
 
 def main():
+    import faulthandler
+    faulthandler.enable()   # a crash in native code prints the Python stack that called it
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -348,6 +350,8 @@ def main():
                     help="also run the uneven batch of 64 instances in one HIP graph (p50/p99 latency)")
     ap.add_argument("--c5-branches", type=int, default=4)
     ap.add_argument("--c5-replays", type=int, default=10)
+    ap.add_argument("--pcg-steps", type=int, default=1,
+                    help="also time this many analyses with the PCG solver (0: skip)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the ring40 and grid96x48 lines (batched vs plain, error vs the whole oracle)")
     ap.add_argument("--adjoint-steps", type=int, default=3,
@@ -536,6 +540,32 @@ def main():
         Xa = step(args.mode)
         Xa_h = Xa.cpu().numpy()
 
+    pcg = None
+    if args.pcg_steps > 0 and args.mode == "batched":
+        # the local systems by B^-preconditioned CG (primal eq. 11), timed
+        # beside the dual form on the same fit
+        plan.fit(Xb, lam, mode=args.mode)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.pcg_steps):
+            Xp = plan.analyze(Xb, Y, r, solver="pcg")
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t) / args.pcg_steps
+        st = plan.pcg_stats()
+        Xd = plan.analyze(Xb, Y, r, solver="dual")
+        d_pcg = float(torch.linalg.norm(Xp - Xd) / torch.linalg.norm(Xd - Xb.double()))
+        dual_ms = sum(phases.get(k, 0.0) for k in ("dual_F", "dual_S", "dual_chol", "dual_Q", "dual_G", "sweep",
+                                                    "mapback"))
+        pcg = {"ms_analyze": tp * 1e3, "ms_analyze_dual_kernels": dual_ms, **st,
+               "increment_rel_diff_vs_dual": d_pcg,
+               "note": "enkfmc_analyze with ENKFMC_SOLVE_PCG (rtol 1e-12 on the preconditioned residual norm, "
+                       "FP64 refinement) after the same batched fit"}
+        log(f"pcg analysis: {tp * 1e3:.1f} ms ({st['iterations']} iterations, largest column "
+            f"{st['max_column_iterations']}, refinements {st['refinements']}) vs {dual_ms:.1f} ms dual; "
+            f"increment differs by {d_pcg:.2e}")
+        Xa = step(args.mode)
+        Xa_h = Xa.cpu().numpy()
+
     small = None
     if not args.no_small and args.mode == "batched":
         small = {}
@@ -574,6 +604,7 @@ def main():
         "adjoint": adjoint,
         "cycles": cyc,
         "svd_fit": svd,
+        "pcg_analysis": pcg,
         "small_workloads": small,
         "uneven_batch_graph": c5,
     }

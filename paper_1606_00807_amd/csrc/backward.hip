@@ -223,6 +223,9 @@ __global__ __launch_bounds__(64) void k_adj_factor_tiles(const Block *__restrict
   dp += __shfl_xor(dp, 16, 64);
   dp += __shfl_xor(dp, 32, 64);
   if (q == 0 && rowc < B.n) dbar[B.row0 + rowc] = dp * dinv * dinv;
+  // CSR range of row c of the tile (the rows the scatter below writes)
+  const int64_t ka = rowc < B.n ? row_ptr[B.row0 + rowc] : 0;
+  const int64_t kend = rowc < B.n ? row_ptr[B.row0 + rowc + 1] : 0;
   for (int t = 0; t <= nt; ++t) {
     const int C = t < nt ? rt_col[t0 + t] : R;
     const int jr = 16 * C + c;                   // row of W_C, Z_C for the B operand
@@ -244,17 +247,15 @@ __global__ __launch_bounds__(64) void k_adj_factor_tiles(const Block *__restrict
 #pragma unroll
     for (int r = 0; r < 4; ++r) sout[(4 * r + q) * 17 + c] = o[r];
     wave_lds_sync();
-    if (lane < 16) {
-      const int row = 16 * R + lane;
-      if (row < B.n) {
-        const int64_t ka = row_ptr[B.row0 + row];
-        const int64_t e0 = ka + teoff[16 * (t0 + rt + t) + lane];
-        const int64_t e1 = t < nt ? ka + teoff[16 * (t0 + rt + t + 1) + lane] : row_ptr[B.row0 + row + 1];
+    // betabar of the entries of row c in this tile (at most 16, consecutive
+    // in CSR order): the four lanes of the row take every fourth
+    if (rowc < B.n) {
+      const int64_t e0 = ka + teoff[16 * (t0 + rt + t) + c];
+      const int64_t e1 = t < nt ? ka + teoff[16 * (t0 + rt + t + 1) + c] : kend;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int64_t k = e0 + e;
-          if (k < e1) bbar[k] = sout[lane * 17 + col[k] - 16 * C];
-        }
+      for (int e = q; e < 16; e += 4) {
+        const int64_t k = e0 + e;
+        if (k < e1) bbar[k] = sout[c * 17 + col[k] - 16 * C];
       }
     }
     wave_lds_sync();
@@ -445,7 +446,8 @@ size_t adj_regress_lds(const enkfmc_plan *p) {
 // over the pattern's tiles (R, C), the diagonal tile included (strictly lower
 // parts); S holds the rows' s in the pattern of T.  One wavefront per (block,
 // column tile); each S_RC is assembled in LDS from the CSR entries, T_RC comes
-// from the dense tiles.  LDS: 16 x 17 doubles.
+// from the dense tiles.  LDS: 16 x 17 doubles.  G = member tiles (N <= 16 G).
+template <int G>
 __global__ __launch_bounds__(64) void k_adj_ubar_tiles(const Block *__restrict__ blocks,
                                                        const int64_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ col,
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(64) void k_adj_ubar_tiles(const Block *__restrict__
                                                        const double *__restrict__ tdiag, const double *__restrict__ sv,
                                                        const double *__restrict__ e1, const double *__restrict__ e2,
                                                        int N, int ntile, double *__restrict__ ubar) {
-  constexpr int kMaxCT = 8;                    // member tiles (N <= 128)
+  constexpr int kMaxCT = G;
   __shared__ double sS[16 * 17];
   int bi, C;
   block_tile(ntile, bi, C);
@@ -482,21 +484,22 @@ __global__ __launch_bounds__(64) void k_adj_ubar_tiles(const Block *__restrict__
     const int R = t < s1 ? ct_row[t] : C;
     const double *Tt = t < s1 ? tiles + (int64_t)ct_slot[t] * 256 : tdiag + (B.rt0 + C) * 256;
     // S_RC: row i of R, columns [16C, 16C + 16); the row's entries of tile
-    // (R, C) start at the planned offset and end where the next tile's begin
-    if (lane < 16) {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) sS[lane * 17 + j] = 0.0;
-      const int row = 16 * R + lane;
+    // (R, C) start at the planned offset and end where the next tile's begin.
+    // Lane (q, c) zeroes every 64th slot, then fills row c's entries q, q + 4, ...
+    for (int e = lane; e < 16 * 17; e += 64) sS[e] = 0.0;
+    wave_lds_sync();
+    {
+      const int row = 16 * R + c;
       if (row < B.n) {
         const int64_t rtR = B.rt0 + R;
-        const int64_t ix = 16 * ((t < s1 ? (int64_t)ct_slot[t] : rt_ptr[rtR + 1]) + rtR) + lane;
+        const int64_t ix = 16 * ((t < s1 ? (int64_t)ct_slot[t] : rt_ptr[rtR + 1]) + rtR) + c;
         const int64_t ka = row_ptr[B.row0 + row];
         const int64_t e0 = ka + teoff[ix];
         const int64_t e1 = t < s1 ? ka + teoff[ix + 16] : row_ptr[B.row0 + row + 1];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = q; e < 16; e += 4) {
           const int64_t k = e0 + e;
-          if (k < e1) sS[lane * 17 + col[k] - 16 * C] = sv[k];
+          if (k < e1) sS[c * 17 + col[k] - 16 * C] = sv[k];
         }
       }
     }
@@ -682,9 +685,21 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   phase_end(p, ENKFMC_PH_ADJ_REGRESS, s);
   phase_begin(p, ENKFMC_PH_ADJ_GATHER, s);
   const int mtu = max_block_tiles(p);
-  hipLaunchKernelGGL(k_adj_ubar_tiles, dim3(nb * (unsigned)mtu), dim3(64), 0, s, d.blocks, d.row_ptr, d.col,
-                     d.rt_ptr, d.tile_eoff, d.ct_ptr, d.ct_row, d.ct_slot, d.tiles, d.tdiag, d.aux3, d.aux1, d.aux2, N,
-                     mtu, d.ubar);
+#define ADJ_UBAR(G)                                                                                              \
+  hipLaunchKernelGGL(k_adj_ubar_tiles<G>, dim3(nb * (unsigned)mtu), dim3(64), 0, s, d.blocks, d.row_ptr, d.col,     \
+                     d.rt_ptr, d.tile_eoff, d.ct_ptr, d.ct_row, d.ct_slot, d.tiles, d.tdiag, d.aux3, d.aux1, d.aux2, \
+                     N, mtu, d.ubar)
+  switch ((N + 15) / 16) {
+    case 1: ADJ_UBAR(1); break;
+    case 2: ADJ_UBAR(2); break;
+    case 3: ADJ_UBAR(3); break;
+    case 4: ADJ_UBAR(4); break;
+    case 5: ADJ_UBAR(5); break;
+    case 6: ADJ_UBAR(6); break;
+    case 7: ADJ_UBAR(7); break;
+    default: ADJ_UBAR(8); break;
+  }
+#undef ADJ_UBAR
   hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)((p->n + 3) / 4)), dim3(256), 0, s, d.g2f_ptr, d.g2f, d.ubar, dXa,
                      p->n, N, dXb);
   if (p->m > 0)
