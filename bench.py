@@ -45,11 +45,48 @@ def fit_flops(counts, N):
     return float(2.0 * fma.sum())
 
 
+def phase_roofline(info, N, phases, xb_bytes, fit_all_flops, fit_kf_flops):
+    """Achieved fraction of every phase of the step against the roof that
+    bounds it, from algorithmic counts (what the phase must read, write or
+    compute; halo redundancy included).  The fit phases are FP64 compute; the
+    analysis phases are priced by the HBM bytes they must move, though most
+    are bound by the latency of their tile streams."""
+    n, nf, ml = info["n"], info["n_fit"], info["m_local"]
+    tiles_b = (info["n_tiles"] + info["n_row_tiles"]) * 2048      # stored T tiles + inverse diagonal tiles
+    alg = {
+        "anomaly": ("hbm", n * N * xb_bytes + n * (-(-N // 16) * 16) * 8 + n * 8),
+        "fit": ("fp64", fit_all_flops),
+        "fit_kform": ("fp64", fit_kf_flops),
+        "tiles": ("hbm", info["nnz"] * 12 + (info["n_tiles"] + 2 * info["n_row_tiles"]) * 2048),
+        "dual_F": ("hbm", tiles_b + info["f_entries"] * 8),
+        "dual_S": ("hbm", info["f_entries"] * 8 + info["s_entries"] * 8 + nf * 8),
+        "dual_chol": ("hbm", info["s_entries"] * 8 * 2),
+        "dual_Q": ("hbm", info["s_entries"] * 8 + ml * N * (8 + xb_bytes) + ml * N * 8),
+        "dual_G": ("hbm", info["f_entries"] * 8 + ml * N * 8 + nf * N * 8),
+        "sweep": ("hbm", tiles_b + nf * N * 8 * 2),
+        "mapback": ("hbm", n * N * (xb_bytes + 8 + 8)),
+    }
+    out = {}
+    for ph, (bound, amount) in alg.items():
+        ms = phases.get(ph, 0.0)
+        if not ms:
+            continue
+        if bound == "fp64":
+            ach = amount / (ms * 1e-3)
+            out[ph] = {"ms": ms, "bound": "fp64", "algorithmic_flops": amount, "achieved": ach / 1e12,
+                       "unit": "TFLOP/s", "frac": ach / PEAK_FP64}
+        else:
+            ach = amount / (ms * 1e-3)
+            out[ph] = {"ms": ms, "bound": "hbm", "algorithmic_bytes": amount, "achieved": ach / 1e9,
+                       "unit": "GB/s", "frac": ach / PEAK_HBM}
+    return out
+
+
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # counters, each scaled by what the same counter reads for a plain copy of
 # known size.  Valid only for the kernel source it was taken on: a changed
 # source reports null.
-TRAFFIC = {"fit_batched_sha256": "8261a959a7206d627b328df3725bdfba16ee862cc3f6796d4e7cdff3021ccada",
+TRAFFIC = {"fit_batched_sha256": "8d2749ba3808771d41da3dc2ca1de7810084fba303825e3163b9427d18dd45fd",
            "fetch_bytes": 1.7592e+09, "write_bytes": 9.1895e+08, "bytes_per_launch": 2.6781e+09,
            "fetch_scale": 1.9999, "write_scale": 1.0}
 
@@ -510,6 +547,7 @@ def main():
                 "bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64, "traffic": tr, "launch_ms": phases["fit_kform"],
                 "rows_per_launch": int(kform.sum()), "algorithmic_flops_per_launch": fk, "fit_phase": fit_all}
+        roof["phases"] = phase_roofline(info, prob.N, phases, prob.Xb.dtype.itemsize, flops, fk)
     else:
         achieved = flops / (phases["fit"] * 1e-3)
         roof = {"kernel": "k_fit_plain" if args.mode == "plain" else "fit", "bound": "alu",

@@ -105,6 +105,10 @@ typedef struct {
   size_t workspace_bytes;  /* device workspace enkfmc_plan_set_workspace needs       */
   int64_t fit_rows_wave;   /* rows ENKFMC_FIT_BATCHED fits with one-wavefront kernels */
   int64_t fit_rows_plain;  /* rows ENKFMC_FIT_BATCHED hands to the plain kernel       */
+  int64_t n_row_tiles;     /* 16-row tiles of T over all blocks                      */
+  int64_t n_tiles;         /* stored off-diagonal 16x16 tiles of T                   */
+  int64_t f_entries;       /* entries of the dual form's F = T^-T H^T, all blocks     */
+  int64_t s_entries;       /* entries of its S = R + F^T D F, all blocks              */
 } enkfmc_plan_info;
 
 /* Build the decomposition of Section 3 (host only, no device work).

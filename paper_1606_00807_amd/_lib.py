@@ -33,7 +33,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n", c_int64), ("N", c_int64), ("m", c_int64), ("n_subdomains", c_int64), ("n_blocks", c_int64),
                 ("n_fit", c_int64), ("nnz", c_int64), ("m_local", c_int64), ("max_p", c_int32),
                 ("max_block_rows", c_int32), ("max_block_obs", c_int32), ("reserved", c_int32),
-                ("workspace_bytes", c_size_t), ("fit_rows_wave", c_int64), ("fit_rows_plain", c_int64)]
+                ("workspace_bytes", c_size_t), ("fit_rows_wave", c_int64), ("fit_rows_plain", c_int64),
+                ("n_row_tiles", c_int64), ("n_tiles", c_int64), ("f_entries", c_int64), ("s_entries", c_int64)]
 
 
 class EnkfmcError(RuntimeError):

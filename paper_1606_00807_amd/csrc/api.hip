@@ -136,6 +136,10 @@ enkfmc_status enkfmc_plan_get_info(const enkfmc_plan *p, enkfmc_plan_info *info)
   info->workspace_bytes = p->lay.total;
   info->fit_rows_plain = p->bucket_off[kBucketPlain + 1] - p->bucket_off[kBucketPlain];
   info->fit_rows_wave = p->n_fit - info->fit_rows_plain;
+  info->n_row_tiles = p->n_rt;
+  info->n_tiles = p->n_slots;
+  info->f_entries = p->sum_F;
+  info->s_entries = p->sum_S;
   return ENKFMC_OK;
 }
 

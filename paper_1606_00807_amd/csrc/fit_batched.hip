@@ -209,100 +209,29 @@ struct AdjIO {
   double *sb;           // per CSR entry: betabar on entry, s on exit
   double *e1, *e2;      // n_fit x N
   double *lam_row;      // per fit row: its share of dL/dlam
-  double *ebl;          // wavefront LDS (16 kMaxT): epsbar of the row, p-form
+  double *ebl;          // wavefront LDS (kMaxP + 8): epsbar (p-form) or b (kernel form) of the row
 };
 
-// Adjoint pre-pass of a kernel-form row r, before its Gram: eps from the
-// stored coefficients, epsbar, b = betabar - U_P epsbar, and the right-hand
-// side U_P^T b in the bordering row.  Leaves e1 = eps/(N-1), e2 = epsbar and
-// sb = b in global memory for the post-pass.  Both passes over U_P load the
-// Gram's fragments (members 16I + c of predecessor 4ks + q), four k-steps of
-// loads at a time; steps past the last read the zero pad row (the pidx index
-// stays below 4 * 32 < kMaxP + 8).
+// Adjoint pre-pass of a kernel-form row r, before its Gram.  In the kernel
+// form the forward solve gave eps = mu w and beta = U_P w for the solution w
+// of (U_P^T U_P + mu I) w = u, so U_P eps = mu beta and
+//   b = betabar - U_P epsbar = betabar - (2 Dbar mu/(N-1)) beta
+// needs no pass over U_P.  This leaves beta and b in LDS (zero past p) for
+// the Gram loop, which sums eps = u - U_P^T beta and U_P^T b from its own
+// fragments, and b in sb for the post-pass.
 template <int T>
-__device__ __forceinline__ void adj_rhs(const int lane, const int64_t r, const int p, const int N,
-                                        const double *__restrict__ U, const int ldu, const int uoff, WaveLds<T> &L,
-                                        const double *__restrict__ tval, const int64_t lo, const AdjIO &adj,
-                                        double (&augv)[T]) {
-  const int q = lane >> 4, c = lane & 15;
-  const double nm1 = (double)(N - 1);
-  const double Db = adj.dbar[r];
-  double *bl = L.tile;             // beta (kMaxP entries)
-  double *el = L.tile + kMaxP;     // epsbar (16 * kMaxT entries)
-  for (int a = lane; a < kMaxP; a += 64) bl[a] = a < p ? -tval[lo + a] : 0.0;
-  wave_lds_sync();
-  const int ks4 = (((p + 3) >> 2) + 3) & ~3;
-  // eps_k = u_k - sum_a beta_a U[P_a][k]: lane (q, c) sums members 16I + c
-  // over predecessors a = q mod 4; the partial sums are then added across q.
-  double e[T];
-#pragma unroll
-  for (int I = 0; I < T; ++I) e[I] = 0.0;
-  for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
-    double f[4][T], bb[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int a = 4 * (ks0 + u) + q;
-      const int off = L.pidx[a] * ldu + c;
-      bb[u] = bl[a];
-#pragma unroll
-      for (int I = 0; I < T; ++I) f[u][I] = U[off + 16 * I];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int I = 0; I < T; ++I) e[I] = fma(bb[u], f[u][I], e[I]);
-  }
-#pragma unroll
-  for (int I = 0; I < T; ++I) {
-    double es = e[I];
-    es = quarter_sum(es);
-    const int k = 16 * I + c;
-    const bool ok = k < N;
-    const double eps = ok ? U[uoff + k] - es : 0.0;
-    const double eb = 2.0 * Db * eps / nm1;
-    if (q == 0) {
-      el[k] = eb;
-      if (ok) {
-        adj.e1[r * N + k] = eps / nm1;
-        adj.e2[r * N + k] = eb;
-      }
-    }
-  }
-  wave_lds_sync();
-  // b_a = betabar_a - sum_k U[P_a][k] epsbar_k (the 16 lanes of each quarter
-  // add up), and (U_P^T b)_k accumulated from the same fragments
-  double ev[T];
-#pragma unroll
-  for (int I = 0; I < T; ++I) ev[I] = el[16 * I + c];
-  double tacc[T];
-#pragma unroll
-  for (int I = 0; I < T; ++I) tacc[I] = 0.0;
-  for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
-    double f[4][T];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int off = L.pidx[4 * (ks0 + u) + q] * ldu + c;
-#pragma unroll
-      for (int I = 0; I < T; ++I) f[u][I] = U[off + 16 * I];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int a = 4 * (ks0 + u) + q;
-      double sm = 0.0;
-#pragma unroll
-      for (int I = 0; I < T; ++I) sm = fma(f[u][I], ev[I], sm);
-      sm = row16_sum(sm);
-      const double b = a < p ? adj.sb[lo + a] - sm : 0.0;
-      if (c == 0 && a < p) adj.sb[lo + a] = b;
-#pragma unroll
-      for (int I = 0; I < T; ++I) tacc[I] = fma(f[u][I], b, tacc[I]);
-    }
-  }
-#pragma unroll
-  for (int I = 0; I < T; ++I) {
-    double t = tacc[I];
-    t = quarter_sum(t);
-    augv[I] = (q == 0 && 16 * I + c < N) ? t : 0.0;
+__device__ __forceinline__ void adj_pre_kf(const int lane, const int64_t r, const int p, const int N,
+                                           const double mu, WaveLds<T> &L, const double *__restrict__ tval,
+                                           const int64_t lo, const AdjIO &adj) {
+  const double coef = 2.0 * adj.dbar[r] * mu / (double)(N - 1);
+  double *bl = L.tile;             // beta
+  double *bv = adj.ebl;            // b
+  for (int a = lane; a < kMaxP + 8; a += 64) {
+    const double beta = a < p ? -tval[lo + a] : 0.0;
+    const double b = a < p ? fma(-coef, beta, adj.sb[lo + a]) : 0.0;
+    if (a < kMaxP) bl[a] = beta;
+    bv[a] = b;
+    if (a < p) adj.sb[lo + a] = b;
   }
   wave_lds_sync();
 }
@@ -318,7 +247,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   double augv[T];   // bordering row: element 16J + c at lane (q = 0, c)
   // kernel form: eps, epsbar and b in passes of their own; the p-form forms
   // them inside its Gram loop below
-  if constexpr (ADJ && KF) adj_rhs<T>(lane, r, p, N, U, ldu, uoff, L, tval, lo, adj, augv);
+  if constexpr (ADJ && KF) adj_pre_kf<T>(lane, r, p, N, mu, L, tval, lo, adj);
   d4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
@@ -338,6 +267,15 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     const int ksn = (p + 3) >> 2;   // k-steps with at least one predecessor
     const int kse = ksn & ~1;        // done in pairs; an odd last step follows the loop
     double fa[T], fb[T];
+    // adjoint: lane (q, c) also sums beta_a U[P_a][k] and b_a U[P_a][k] over
+    // its predecessors a = 4ks + q for members k = 16I + c (eps and U_P^T b),
+    // VALU work that runs beside the Gram's products
+    double ea[T], ta[T];
+    const double *blp = L.tile, *bvp = adj.ebl;
+    if constexpr (ADJ) {
+#pragma unroll
+      for (int I = 0; I < T; ++I) ea[I] = ta[I] = 0.0;
+    }
     {
       const int off = L.pidx[q] * ldu + c;
 #pragma unroll
@@ -352,6 +290,14 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       for (int I = 0; I < T; ++I)
 #pragma unroll
         for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
+      if constexpr (ADJ) {
+        const double bb = blp[4 * ks + q], bw = bvp[4 * ks + q];
+#pragma unroll
+        for (int I = 0; I < T; ++I) {
+          ea[I] = fma(bb, fa[I], ea[I]);
+          ta[I] = fma(bw, fa[I], ta[I]);
+        }
+      }
       __builtin_amdgcn_sched_barrier(0);
       const int offa = L.pidx[4 * ks + 8 + q] * ldu + c;
 #pragma unroll
@@ -361,6 +307,14 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       for (int I = 0; I < T; ++I)
 #pragma unroll
         for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fb[J], fb[I], acc[tix<T>(I, J)]);
+      if constexpr (ADJ) {
+        const double bb = blp[4 * ks + 4 + q], bw = bvp[4 * ks + 4 + q];
+#pragma unroll
+        for (int I = 0; I < T; ++I) {
+          ea[I] = fma(bb, fb[I], ea[I]);
+          ta[I] = fma(bw, fb[I], ta[I]);
+        }
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
     if (ksn & 1) {   // the last prefetch holds k-step ksn - 1
@@ -368,6 +322,33 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       for (int I = 0; I < T; ++I)
 #pragma unroll
         for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
+      if constexpr (ADJ) {
+        const double bb = blp[4 * kse + q], bw = bvp[4 * kse + q];
+#pragma unroll
+        for (int I = 0; I < T; ++I) {
+          ea[I] = fma(bb, fa[I], ea[I]);
+          ta[I] = fma(bw, fa[I], ta[I]);
+        }
+      }
+    }
+    if constexpr (ADJ) {
+      // eps_k = u_k - (U_P^T beta)_k, epsbar = 2 Dbar eps/(N-1): e1 = eps/(N-1)
+      // and e2 = epsbar for the post-pass; the bordering row is U_P^T b
+      const double nm1 = (double)(N - 1);
+      const double Db = adj.dbar[r];
+#pragma unroll
+      for (int I = 0; I < T; ++I) {
+        const double es = quarter_sum(ea[I]);
+        const double tb = quarter_sum(ta[I]);
+        const int k = 16 * I + c;
+        const bool ok = k < N;
+        const double eps = ok ? U[uoff + k] - es : 0.0;
+        if (q == 0 && ok) {
+          adj.e1[r * N + k] = eps / nm1;
+          adj.e2[r * N + k] = 2.0 * Db * eps / nm1;
+        }
+        augv[I] = (q == 0 && ok) ? tb : 0.0;
+      }
     }
     if constexpr (!ADJ) {
 #pragma unroll
@@ -795,7 +776,7 @@ __global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_b
     int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, double lam, double *__restrict__ tval,
     AdjIO adj, int32_t *status) {
   __shared__ WaveLds<T> lds[4];
-  __shared__ double ebl[4][16 * kMaxT];
+  __shared__ double ebl[4][kMaxP + 8];   // epsbar (p-form, 16 kMaxT used) or b (kernel form)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
   if (idx >= nrows) return;
