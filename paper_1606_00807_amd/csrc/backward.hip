@@ -143,122 +143,129 @@ __global__ __launch_bounds__(64) void k_adj_solve_S(const Block *__restrict__ bl
   for (int a = m; a < lds; ++a) x[(int64_t)a * N + c] = 0.0;
 }
 
-// Dbar and betabar by 16-row tiles of T.  One wavefront per (block, row tile
-// R).  First TZ_R = Z_R + sum_C T_RC Z_C and TW_R likewise (C over the
-// pattern's tiles of R, the strictly lower T_RR included), accumulated
-// transposed: with the operands of each v_mfma_f64_16x16x4 swapped, member
-// tile g's accumulator holds (TZ_R)^T, so lane (q, c) keeps rows c of TZ_R and
-// TW_R at members 16g + 4r + q -- exactly the A operands the 16 x 16 products
-// below need, so they stay in registers (scaled by 1/d_c).
-// Dbar_i = (TW)_i . (TZ)_i / d_i^2 is a sum over each lane's members and then
-// over the four rows of 16 lanes.  Then per tile (R, C) of the pattern the
-// products (TZ_R/d) W_C^T + (TW_R/d) Z_C^T, of which the entries in the
-// pattern of T are betabar, written in CSR order through a 16 x 17 LDS tile.
+// Dbar and betabar by 16-row tiles of T.  One workgroup per (block, row tile
+// R), one wavefront per member tile g (N <= 16 G).  First TZ_R = Z_R +
+// sum_C T_RC Z_C and TW_R likewise (C over the pattern's tiles of R, the
+// strictly lower T_RR included), over the wave's 16 members, accumulated
+// transposed: with the operands of each v_mfma_f64_16x16x4 swapped, the
+// accumulator holds (TZ_R)^T, so lane (q, c) keeps row c of TZ_R and TW_R at
+// members 16g + 4r + q -- exactly the A operands the 16 x 16 products below
+// need, so they stay in registers (scaled by 1/d_c).
+// Dbar_i = (TW)_i . (TZ)_i / d_i^2: each wave sums its members, the partials
+// meet in LDS and are added in member-tile order.  Then per tile (R, C) of the
+// pattern each wave forms its members' share of (TZ_R/d) W_C^T + (TW_R/d)
+// Z_C^T; the shares are added in LDS in member-tile order, and the entries in
+// the pattern of T are betabar, written in CSR order.
 template <int G>
-__global__ __launch_bounds__(64) void k_adj_factor_tiles(const Block *__restrict__ blocks,
-                                                         const int64_t *__restrict__ row_ptr,
-                                                         const int32_t *__restrict__ col,
-                                                         const int64_t *__restrict__ rt_ptr,
-                                                         const int32_t *__restrict__ rt_col,
-                                                         const int32_t *__restrict__ rt_slot,
-                                                         const uint16_t *__restrict__ teoff,
-                                                         const double *__restrict__ tiles,
-                                                         const double *__restrict__ tdiag,
-                                                         const double *__restrict__ dvec, const double *__restrict__ Z,
-                                                         const double *__restrict__ W, int N, int ntile,
-                                                         double *__restrict__ dbar, double *__restrict__ bbar) {
-  __shared__ double sout[16 * 17];
+__global__ __launch_bounds__(64 * G) void k_adj_factor_tiles(const Block *__restrict__ blocks,
+                                                             const int64_t *__restrict__ row_ptr,
+                                                             const int32_t *__restrict__ col,
+                                                             const int64_t *__restrict__ rt_ptr,
+                                                             const int32_t *__restrict__ rt_col,
+                                                             const int32_t *__restrict__ rt_slot,
+                                                             const uint16_t *__restrict__ teoff,
+                                                             const double *__restrict__ tiles,
+                                                             const double *__restrict__ tdiag,
+                                                             const double *__restrict__ dvec,
+                                                             const double *__restrict__ Z,
+                                                             const double *__restrict__ W, int N, int ntile,
+                                                             double *__restrict__ dbar, double *__restrict__ bbar) {
+  __shared__ double sred[2][G][16 * 17];   // per-wave 16 x 16 shares, double-buffered over tiles
+  __shared__ double sdp[G][16];
+  __shared__ int64_t srow[2][16];          // CSR start and end of the tile's rows
   int bi, R;
   block_tile(ntile, bi, R);
   const Block B = blocks[bi];
   if (R >= B.nrt) return;
-  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int tid = threadIdx.x, g = tid >> 6, lane = tid & 63, q = lane >> 4, c = lane & 15;
   const int64_t rt = B.rt0 + R;
   const int64_t t0 = rt_ptr[rt];
   const int nt = (int)(rt_ptr[rt + 1] - t0);
   const double *Zb = Z + B.row0 * N, *Wb = W + B.row0 * N;
   const int rowc = 16 * R + c;                   // the row this lane's accumulators hold
   const double dinv = rowc < B.n ? 1.0 / dvec[B.row0 + rowc] : 0.0;
-  d4 az[G], aw[G];
+  if (tid < 16) {
+    const int row = 16 * R + tid;
+    srow[0][tid] = row < B.n ? row_ptr[B.row0 + row] : 0;
+    srow[1][tid] = row < B.n ? row_ptr[B.row0 + row + 1] : 0;
+  }
+  const int mc = 16 * g + c;                     // member of this lane's A operands below
+  const bool mok = mc < N;
+  d4 az, aw;
   // identity part: (Z_R)^T at lane (q, c), register r: Z[16R + c][16g + 4r + q]
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = 16 * g + 4 * r + q;
-      const bool in = rowc < B.n && m < N;
-      az[g][r] = in ? Zb[(int64_t)rowc * N + m] : 0.0;
-      aw[g][r] = in ? Wb[(int64_t)rowc * N + m] : 0.0;
-    }
+  for (int r = 0; r < 4; ++r) {
+    const int m = 16 * g + 4 * r + q;
+    const bool in = rowc < B.n && m < N;
+    az[r] = in ? Zb[(int64_t)rowc * N + m] : 0.0;
+    aw[r] = in ? Wb[(int64_t)rowc * N + m] : 0.0;
   }
   for (int t = 0; t <= nt; ++t) {                // t == nt: the diagonal tile
     const int C = t < nt ? rt_col[t0 + t] : R;
     const double *Tt = t < nt ? tiles + (int64_t)rt_slot[t0 + t] * 256 : tdiag + rt * 256;
-    double tb[4];
 #pragma unroll
-    for (int kc = 0; kc < 4; ++kc) tb[kc] = Tt[c * 16 + 4 * kc + q];   // B operand: T_RC^T[4kc + q][c]
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int m = 16 * g + c;
-      const bool min = m < N;
-#pragma unroll
-      for (int kc = 0; kc < 4; ++kc) {
-        const int zr = 16 * C + 4 * kc + q;      // A operand: Z_C^T[m][4kc + q]
-        const bool in = zr < B.n && min;
-        az[g] = mfma64(in ? Zb[(int64_t)zr * N + m] : 0.0, tb[kc], az[g]);
-        aw[g] = mfma64(in ? Wb[(int64_t)zr * N + m] : 0.0, tb[kc], aw[g]);
-      }
+    for (int kc = 0; kc < 4; ++kc) {
+      const double tb = Tt[c * 16 + 4 * kc + q];   // B operand: T_RC^T[4kc + q][c]
+      const int zr = 16 * C + 4 * kc + q;          // A operand: Z_C^T[mc][4kc + q]
+      const bool in = zr < B.n && mok;
+      az = mfma64(in ? Zb[(int64_t)zr * N + mc] : 0.0, tb, az);
+      aw = mfma64(in ? Wb[(int64_t)zr * N + mc] : 0.0, tb, aw);
     }
   }
   double dp = 0.0;
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      dp = fma(az[g][r], aw[g][r], dp);
-      az[g][r] *= dinv;
-      aw[g][r] *= dinv;
-    }
+  for (int r = 0; r < 4; ++r) {
+    dp = fma(az[r], aw[r], dp);
+    az[r] *= dinv;
+    aw[r] *= dinv;
   }
   dp += __shfl_xor(dp, 16, 64);
   dp += __shfl_xor(dp, 32, 64);
-  if (q == 0 && rowc < B.n) dbar[B.row0 + rowc] = dp * dinv * dinv;
-  // CSR range of row c of the tile (the rows the scatter below writes)
-  const int64_t ka = rowc < B.n ? row_ptr[B.row0 + rowc] : 0;
-  const int64_t kend = rowc < B.n ? row_ptr[B.row0 + rowc + 1] : 0;
+  if (q == 0) sdp[g][c] = dp;
+  __syncthreads();
+  if (tid < 16 && rowc < B.n) {                  // wave 0, q == 0: row c == tid
+    double s = 0.0;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) s += sdp[gg][tid];
+    dbar[B.row0 + rowc] = s * dinv * dinv;
+  }
   for (int t = 0; t <= nt; ++t) {
     const int C = t < nt ? rt_col[t0 + t] : R;
     const int jr = 16 * C + c;                   // row of W_C, Z_C for the B operand
     const bool jin = jr < B.n;
     d4 o1 = d4{0.0, 0.0, 0.0, 0.0}, o2 = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = 16 * g + 4 * r + q;        // k-step 4g + r: members 16g + 4r + q
-        const bool in = jin && k < N;
-        const double bw = in ? Wb[(int64_t)jr * N + k] : 0.0;
-        const double bz = in ? Zb[(int64_t)jr * N + k] : 0.0;
-        o1 = mfma64(az[g][r], bw, o1);
-        o2 = mfma64(aw[g][r], bz, o2);
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int k = 16 * g + 4 * r + q;          // k-step r: members 16g + 4r + q
+      const bool in = jin && k < N;
+      const double bw = in ? Wb[(int64_t)jr * N + k] : 0.0;
+      const double bz = in ? Zb[(int64_t)jr * N + k] : 0.0;
+      o1 = mfma64(az[r], bw, o1);
+      o2 = mfma64(aw[r], bz, o2);
     }
     const d4 o = o1 + o2;
+    double *so = sred[t & 1][g];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sout[(4 * r + q) * 17 + c] = o[r];
-    wave_lds_sync();
-    // betabar of the entries of row c in this tile (at most 16, consecutive
-    // in CSR order): the four lanes of the row take every fourth
-    if (rowc < B.n) {
-      const int64_t e0 = ka + teoff[16 * (t0 + rt + t) + c];
-      const int64_t e1 = t < nt ? ka + teoff[16 * (t0 + rt + t + 1) + c] : kend;
+    for (int r = 0; r < 4; ++r) so[(4 * r + q) * 17 + c] = o[r];
+    __syncthreads();
+    // betabar of the entries of tile row i (at most 16, consecutive in CSR
+    // order): thread (i, e) takes entry e of row i
+    const double(*sb)[16 * 17] = sred[t & 1];
+    for (int pr = tid; pr < 256; pr += 64 * G) {
+      const int i = pr >> 4, e = pr & 15;
+      if (16 * R + i >= B.n) continue;
+      const int64_t ka = srow[0][i];
+      const int64_t e0 = ka + teoff[16 * (t0 + rt + t) + i];
+      const int64_t e1 = t < nt ? ka + teoff[16 * (t0 + rt + t + 1) + i] : srow[1][i];
+      const int64_t k = e0 + e;
+      if (k < e1) {
+        const int j = i * 17 + col[k] - 16 * C;
+        double v = 0.0;
 #pragma unroll
-      for (int e = q; e < 16; e += 4) {
-        const int64_t k = e0 + e;
-        if (k < e1) bbar[k] = sout[c * 17 + col[k] - 16 * C];
+        for (int gg = 0; gg < G; ++gg) v += sb[gg][j];
+        bbar[k] = v;
       }
     }
-    wave_lds_sync();
   }
 }
 
@@ -444,98 +451,120 @@ size_t adj_regress_lds(const enkfmc_plan *p) {
 // Ubar of every fit row by 16-row column tiles: for column tile C of a block,
 //   Ubar_C = sum_R (S_RC^T E1_R - T_RC^T E2_R) - E2_C
 // over the pattern's tiles (R, C), the diagonal tile included (strictly lower
-// parts); S holds the rows' s in the pattern of T.  One wavefront per (block,
-// column tile); each S_RC is assembled in LDS from the CSR entries, T_RC comes
-// from the dense tiles.  LDS: 16 x 17 doubles.  G = member tiles (N <= 16 G).
+// parts); S holds the rows' s in the pattern of T.  One workgroup per (block,
+// column tile), one wavefront per member tile g (N <= 16 G): the members are
+// independent columns of the products.  The workgroup assembles each S_RC in
+// LDS from the CSR entries (double-buffered over tiles); T_RC comes from the
+// dense tiles.
 template <int G>
-__global__ __launch_bounds__(64) void k_adj_ubar_tiles(const Block *__restrict__ blocks,
-                                                       const int64_t *__restrict__ row_ptr,
-                                                       const int32_t *__restrict__ col,
-                                                       const int64_t *__restrict__ rt_ptr,
-                                                       const uint16_t *__restrict__ teoff,
-                                                       const int64_t *__restrict__ ct_ptr,
-                                                       const int32_t *__restrict__ ct_row,
-                                                       const int32_t *__restrict__ ct_slot,
-                                                       const double *__restrict__ tiles,
-                                                       const double *__restrict__ tdiag, const double *__restrict__ sv,
-                                                       const double *__restrict__ e1, const double *__restrict__ e2,
-                                                       int N, int ntile, double *__restrict__ ubar) {
-  constexpr int kMaxCT = G;
-  __shared__ double sS[16 * 17];
+__global__ __launch_bounds__(64 * G) void k_adj_ubar_tiles(const Block *__restrict__ blocks,
+                                                           const int64_t *__restrict__ row_ptr,
+                                                           const int32_t *__restrict__ col,
+                                                           const int64_t *__restrict__ rt_ptr,
+                                                           const uint16_t *__restrict__ teoff,
+                                                           const int64_t *__restrict__ ct_ptr,
+                                                           const int32_t *__restrict__ ct_row,
+                                                           const int32_t *__restrict__ ct_slot,
+                                                           const double *__restrict__ tiles,
+                                                           const double *__restrict__ tdiag,
+                                                           const double *__restrict__ sv,
+                                                           const double *__restrict__ e1,
+                                                           const double *__restrict__ e2, int N, int ntile,
+                                                           double *__restrict__ ubar) {
+  __shared__ double sS[2][16 * 17];
   int bi, C;
   block_tile(ntile, bi, C);
   const Block B = blocks[bi];
   if (C >= B.nrt) return;
-  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
-  const int nct = (N + 15) >> 4;
+  const int tid = threadIdx.x, g = tid >> 6, lane = tid & 63, q = lane >> 4, c = lane & 15;
   const double *E1 = e1 + B.row0 * N, *E2 = e2 + B.row0 * N;
-  d4 acc[kMaxCT];
+  const int colj = 16 * g + c;                   // this lane's member
+  const bool colok = colj < N;
+  d4 acc;
 #pragma unroll
-  for (int cc = 0; cc < kMaxCT; ++cc) {
-    const int colj = 16 * cc + c;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * C + 4 * r + q;
-      acc[cc][r] = (cc < nct && colj < N && row < B.n) ? -E2[(int64_t)row * N + colj] : 0.0;
-    }
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * C + 4 * r + q;
+    acc[r] = (colok && row < B.n) ? -E2[(int64_t)row * N + colj] : 0.0;
   }
   const int64_t s0 = ct_ptr[B.rt0 + C], s1 = ct_ptr[B.rt0 + C + 1];
-  for (int64_t t = s0; t <= s1; ++t) {         // t == s1: the diagonal tile (R = C)
+  // Per tile (t == s1: the diagonal tile, R = C): the A operands -(T_RC^T)[c][k]
+  // (k = 4kc + q), the B operands E1_R, E2_R at rows 16R + k, and the entries
+  // of S_RC this thread places: thread (i, e) takes entry e of row i of R
+  // within the tile's columns [16C, 16C + 16) (the row's entries of tile (R,
+  // C) start at the planned offset and end where the next tile's begin), kept
+  // as its slot in the 16 x 17 tile and its value.  Loaded one tile ahead.
+  constexpr int kPairs = (256 + 64 * G - 1) / (64 * G);
+  auto load = [&](int64_t t, double (&at)[4], double (&b1)[4], double (&b2)[4], int (&js)[kPairs],
+                  double (&vs)[kPairs]) {
     const int R = t < s1 ? ct_row[t] : C;
     const double *Tt = t < s1 ? tiles + (int64_t)ct_slot[t] * 256 : tdiag + (B.rt0 + C) * 256;
-    // S_RC: row i of R, columns [16C, 16C + 16); the row's entries of tile
-    // (R, C) start at the planned offset and end where the next tile's begin.
-    // Lane (q, c) zeroes every 64th slot, then fills row c's entries q, q + 4, ...
-    for (int e = lane; e < 16 * 17; e += 64) sS[e] = 0.0;
-    wave_lds_sync();
-    {
-      const int row = 16 * R + c;
-      if (row < B.n) {
-        const int64_t rtR = B.rt0 + R;
-        const int64_t ix = 16 * ((t < s1 ? (int64_t)ct_slot[t] : rt_ptr[rtR + 1]) + rtR) + c;
-        const int64_t ka = row_ptr[B.row0 + row];
-        const int64_t e0 = ka + teoff[ix];
-        const int64_t e1 = t < s1 ? ka + teoff[ix + 16] : row_ptr[B.row0 + row + 1];
 #pragma unroll
-        for (int e = q; e < 16; e += 4) {
-          const int64_t k = e0 + e;
-          if (k < e1) sS[c * 17 + col[k] - 16 * C] = sv[k];
+    for (int kc = 0; kc < 4; ++kc) {
+      at[kc] = -Tt[(4 * kc + q) * 16 + c];
+      const int er = 16 * R + 4 * kc + q;
+      const bool in = er < B.n && colok;
+      b1[kc] = in ? E1[(int64_t)er * N + colj] : 0.0;
+      b2[kc] = in ? E2[(int64_t)er * N + colj] : 0.0;
+    }
+    const int64_t rtR = B.rt0 + R;
+#pragma unroll
+    for (int it = 0; it < kPairs; ++it) {
+      const int pr = tid + 64 * G * it;
+      js[it] = -1;
+      vs[it] = 0.0;
+      const int i = (pr >> 4) & 15, e = pr & 15;
+      const int row = 16 * R + i;
+      if (pr < 256 && row < B.n) {
+        const int64_t ix = 16 * ((t < s1 ? (int64_t)ct_slot[t] : rt_ptr[rtR + 1]) + rtR) + i;
+        const int64_t ka = row_ptr[B.row0 + row];
+        const int64_t ea = ka + teoff[ix];
+        const int64_t eb = t < s1 ? ka + teoff[ix + 16] : row_ptr[B.row0 + row + 1];
+        const int64_t k = ea + e;
+        if (k < eb) {
+          js[it] = i * 17 + col[k] - 16 * C;
+          vs[it] = sv[k];
         }
       }
     }
-    wave_lds_sync();
-    // A operands: (S_RC^T)[c][k] = S_RC[k][c] and -(T_RC^T)[c][k], k = 4kc + q
-    double as[4], at[4];
+  };
+  double at[4], b1[4], b2[4], vs[kPairs];
+  int js[kPairs];
+  load(s0, at, b1, b2, js, vs);
+  for (int64_t t = s0; t <= s1; ++t) {
+    double at2[4], b12[4], b22[4], vs2[kPairs];
+    int js2[kPairs];
+    load(t < s1 ? t + 1 : s1, at2, b12, b22, js2, vs2);
+    double *S = sS[(t - s0) & 1];
+    for (int e = tid; e < 16 * 17; e += 64 * G) S[e] = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kPairs; ++it)
+      if (js[it] >= 0) S[js[it]] = vs[it];
+    __syncthreads();
+    // A operands (S_RC^T)[c][k] = S_RC[k][c] with the products
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
-      as[kc] = sS[(4 * kc + q) * 17 + c];
-      at[kc] = -Tt[(4 * kc + q) * 16 + c];
+      acc = mfma64(S[(4 * kc + q) * 17 + c], b1[kc], acc);
+      acc = mfma64(at[kc], b2[kc], acc);
     }
 #pragma unroll
-    for (int cc = 0; cc < kMaxCT; ++cc) {
-      if (cc >= nct) break;
-      const int colj = 16 * cc + c;
-      const bool colok = colj < N;
-#pragma unroll
-      for (int kc = 0; kc < 4; ++kc) {
-        const int er = 16 * R + 4 * kc + q;
-        const bool in = er < B.n && colok;
-        acc[cc] = mfma64(as[kc], in ? E1[(int64_t)er * N + colj] : 0.0, acc[cc]);
-        acc[cc] = mfma64(at[kc], in ? E2[(int64_t)er * N + colj] : 0.0, acc[cc]);
-      }
+    for (int kc = 0; kc < 4; ++kc) {
+      at[kc] = at2[kc];
+      b1[kc] = b12[kc];
+      b2[kc] = b22[kc];
     }
-    wave_lds_sync();
+#pragma unroll
+    for (int it = 0; it < kPairs; ++it) {
+      js[it] = js2[it];
+      vs[it] = vs2[it];
+    }
   }
+  if (!colok) return;
   double *Ub = ubar + B.row0 * N;
 #pragma unroll
-  for (int cc = 0; cc < kMaxCT; ++cc) {
-    const int colj = 16 * cc + c;
-    if (cc >= nct || colj >= N) continue;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * C + 4 * r + q;
-      if (row < B.n) Ub[(int64_t)row * N + colj] = acc[cc][r];
-    }
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * C + 4 * r + q;
+    if (row < B.n) Ub[(int64_t)row * N + colj] = acc[r];
   }
 }
 
@@ -659,7 +688,7 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   {
     const int mt = max_block_tiles(p);
 #define ADJ_FACTOR(G)                                                                                           \
-  hipLaunchKernelGGL(k_adj_factor_tiles<G>, dim3(nb * (unsigned)mt), dim3(64), 0, s, d.blocks, d.row_ptr, d.col, \
+  hipLaunchKernelGGL(k_adj_factor_tiles<G>, dim3(nb * (unsigned)mt), dim3(64 * G), 0, s, d.blocks, d.row_ptr, d.col, \
                      d.rt_ptr, d.rt_col, d.rt_slot, d.tile_eoff, d.tiles, d.tdiag, d.dvec, d.Z, d.W, N, mt, d.dbar, \
                      d.aux3)
     switch ((N + 15) / 16) {   // member tiles kept in registers (N <= 128)
@@ -686,7 +715,7 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   phase_begin(p, ENKFMC_PH_ADJ_GATHER, s);
   const int mtu = max_block_tiles(p);
 #define ADJ_UBAR(G)                                                                                              \
-  hipLaunchKernelGGL(k_adj_ubar_tiles<G>, dim3(nb * (unsigned)mtu), dim3(64), 0, s, d.blocks, d.row_ptr, d.col,     \
+  hipLaunchKernelGGL(k_adj_ubar_tiles<G>, dim3(nb * (unsigned)mtu), dim3(64 * G), 0, s, d.blocks, d.row_ptr, d.col,     \
                      d.rt_ptr, d.tile_eoff, d.ct_ptr, d.ct_row, d.ct_slot, d.tiles, d.tdiag, d.aux3, d.aux1, d.aux2, \
                      N, mtu, d.ubar)
   switch ((N + 15) / 16) {
