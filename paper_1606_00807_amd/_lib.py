@@ -34,7 +34,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_fit", c_int64), ("nnz", c_int64), ("m_local", c_int64), ("max_p", c_int32),
                 ("max_block_rows", c_int32), ("max_block_obs", c_int32), ("reserved", c_int32),
                 ("workspace_bytes", c_size_t), ("fit_rows_wave", c_int64), ("fit_rows_plain", c_int64),
-                ("n_row_tiles", c_int64), ("n_tiles", c_int64), ("f_entries", c_int64), ("s_entries", c_int64)]
+                ("n_row_tiles", c_int64), ("n_tiles", c_int64), ("f_entries", c_int64), ("s_entries", c_int64),
+                ("factor_cache_bytes", c_size_t)]
 
 
 class EnkfmcError(RuntimeError):
@@ -50,6 +51,7 @@ SIGNATURES = {
     "enkfmc_plan_create": (c_int32, [POINTER(c_void_p), POINTER(Geometry), c_int32, POINTER(c_int32), c_int32]),
     "enkfmc_plan_get_info": (c_int32, [c_void_p, POINTER(PlanInfo)]),
     "enkfmc_plan_set_workspace": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "enkfmc_plan_set_factor_cache": (c_int32, [c_void_p, c_void_p, c_size_t]),
     "enkfmc_fit": (c_int32, [c_void_p, c_void_p, c_int32, c_int64, c_double, c_int32, c_void_p]),
     "enkfmc_analyze": (c_int32, [c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_int32,
                                  c_int32, c_void_p]),

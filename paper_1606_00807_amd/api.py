@@ -90,6 +90,7 @@ class Plan:
             self.lib.enkfmc_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
         self.workspace = None
+        self._factor_cache = None
 
     def __del__(self):
         try:
@@ -163,6 +164,25 @@ class Plan:
             check(self.lib.enkfmc_plan_set_workspace(self._h, ctypes.c_void_p(aligned), ctypes.c_size_t(nbytes),
                                                      self._stream()))
         return self.workspace
+
+    def set_factor_cache(self, enable: bool = True) -> int:
+        """Keep the kernel-form regressions' Cholesky tiles from each batched
+        fit (with a ridge) in device memory owned by this object, so that the
+        reverse pass reads them instead of recomputing each row's Gram and
+        factorisation.  Returns the bytes held (0 when disabled)."""
+        import torch
+        check(self.lib.enkfmc_plan_set_factor_cache(self._h, None, ctypes.c_size_t(0)))
+        self._factor_cache = None
+        if not enable:
+            return 0
+        nbytes = int(self.info["factor_cache_bytes"])
+        if nbytes == 0:
+            return 0
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        aligned = (buf.data_ptr() + 255) & ~255
+        check(self.lib.enkfmc_plan_set_factor_cache(self._h, ctypes.c_void_p(aligned), ctypes.c_size_t(nbytes)))
+        self._factor_cache = buf
+        return nbytes
 
     @staticmethod
     def _xb_args(Xb):

@@ -76,6 +76,14 @@ static enkfmc_status finish(enkfmc_plan *p, hipStream_t s, const char *what) {
   return decode_status(st, what);
 }
 
+// Bytes of the kernel-form factor cache: the factored tiles of every row of
+// the kernel-form bucket, T(T + 1)/2 tiles of 256 doubles each, T = ceil(N/16).
+static size_t factor_cache_bytes(const enkfmc_plan *p) {
+  const int64_t nk = p->bucket_off[kBucketKF + 1] - p->bucket_off[kBucketKF];
+  const size_t T = (size_t)(p->N + 15) / 16;
+  return (size_t)nk * (T * (T + 1) / 2) * 256 * sizeof(double);
+}
+
 static enkfmc_status begin(enkfmc_plan *p, hipStream_t s, const char *what) {
   if (!p->ws) return fail(ENKFMC_ESTATE, std::string(what) + ": no workspace (call enkfmc_plan_set_workspace)");
   int dev = -1;
@@ -140,6 +148,24 @@ enkfmc_status enkfmc_plan_get_info(const enkfmc_plan *p, enkfmc_plan_info *info)
   info->n_tiles = p->n_slots;
   info->f_entries = p->sum_F;
   info->s_entries = p->sum_S;
+  info->factor_cache_bytes = factor_cache_bytes(p);
+  return ENKFMC_OK;
+}
+
+enkfmc_status enkfmc_plan_set_factor_cache(enkfmc_plan *p, void *dev, size_t bytes) {
+  if (!p) return fail(ENKFMC_EINVAL, "set_factor_cache: NULL plan");
+  p->fcache_valid = 0;
+  if (!dev) {
+    p->fcache = nullptr;
+    return ENKFMC_OK;
+  }
+  if ((reinterpret_cast<uintptr_t>(dev) & 255) != 0)
+    return fail(ENKFMC_EINVAL, "set_factor_cache: not 256-byte aligned");
+  const size_t need = factor_cache_bytes(p);
+  if (bytes < need)
+    return fail(ENKFMC_ENOMEM, "set_factor_cache: need " + std::to_string(need) + " bytes, got " +
+                                   std::to_string(bytes));
+  p->fcache = (double *)dev;
   return ENKFMC_OK;
 }
 
@@ -198,6 +224,7 @@ enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t 
   enkfmc_status st = begin(p, s, "fit");
   if (st != ENKFMC_OK) return st;
   p->fitted = p->analyzed = 0;
+  p->fcache_valid = 0;
   const Dev d = make_dev(p);
   HIPCHK(launch_anomaly(p, d, Xb, dtype, ld, s), "fit: anomaly launch");
   const bool plain_rows = mode == ENKFMC_FIT_PLAIN ||
@@ -217,6 +244,7 @@ enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t 
   st = finish(p, s, "fit");
   if (st != ENKFMC_OK) return st;
   p->fitted = 1;
+  p->fcache_valid = mode == ENKFMC_FIT_BATCHED && ridge > 0.0 && p->fcache != nullptr;
   p->fit_mode = mode;
   p->fit_ridge = ridge;
   p->fit_xb = Xb;

@@ -38,6 +38,14 @@
 // (U_P U_P^T + mu I)^-1 = [I - U_P (U_P^T U_P + mu I)^-1 U_P^T]/mu) is formed
 // before the Gram, and the same Gram, Cholesky and back substitution follow.
 //
+// Factor cache (kernel form).  Given a cache slot, the fit stores the factored
+// tiles of each kernel-form row (L_IJ^T below the diagonal, L_JJ^-T on it, as
+// step 3 leaves them in registers: NT tiles of 64 lanes x 4 doubles, each lane
+// its own 32 contiguous bytes).  The adjoint instantiated with CACHED loads
+// them instead of recomputing the Gram and the Cholesky: its loop over U_P
+// only sums eps and U_P^T b, and the bordering row's L^-1 v, which the
+// elimination would have produced, comes from a blocked forward substitution.
+//
 // Layout of a v_mfma_f64_16x16x4 accumulator (lane l = 16q + c, register r):
 // element (4r + q, c).  A operand: lane l holds A[c][q]; B operand: B[q][c].
 #include "device.h"
@@ -236,11 +244,12 @@ __device__ __forceinline__ void adj_pre_kf(const int lane, const int64_t r, cons
   wave_lds_sync();
 }
 
-template <int T, bool KF, int MT, bool ADJ = false>
+template <int T, bool KF, int MT, bool ADJ = false, bool CACHED = false>
 __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const int p, const int N, const double mu,
                                         const double *__restrict__ U, const int ldu, const int uoff, WaveLds<T> &L,
                                         double *__restrict__ tval, const int64_t lo, double *__restrict__ dvec,
-                                        int32_t *status, const AdjIO &adj) {
+                                        int32_t *status, const AdjIO &adj, double *__restrict__ fc = nullptr) {
+  static_assert(!CACHED || (KF && ADJ), "only the kernel-form adjoint reads cached factors");
   constexpr int NT = T * (T + 1) / 2;
   const int q = lane >> 4, c = lane & 15;
   const int m = KF ? N : p;
@@ -286,10 +295,12 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
       for (int I = 0; I < T; ++I) fb[I] = U[offb + 16 * I];
       __builtin_amdgcn_sched_barrier(0);   // keep each half's loads ahead of the other half's products
+      if constexpr (!CACHED) {
 #pragma unroll
-      for (int I = 0; I < T; ++I)
+        for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
+      }
       if constexpr (ADJ) {
         const double bb = blp[4 * ks + q], bw = bvp[4 * ks + q];
 #pragma unroll
@@ -303,10 +314,12 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
       for (int I = 0; I < T; ++I) fa[I] = U[offa + 16 * I];
       __builtin_amdgcn_sched_barrier(0);
+      if constexpr (!CACHED) {
 #pragma unroll
-      for (int I = 0; I < T; ++I)
+        for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fb[J], fb[I], acc[tix<T>(I, J)]);
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fb[J], fb[I], acc[tix<T>(I, J)]);
+      }
       if constexpr (ADJ) {
         const double bb = blp[4 * ks + 4 + q], bw = bvp[4 * ks + 4 + q];
 #pragma unroll
@@ -318,10 +331,12 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       __builtin_amdgcn_sched_barrier(0);
     }
     if (ksn & 1) {   // the last prefetch holds k-step ksn - 1
+      if constexpr (!CACHED) {
 #pragma unroll
-      for (int I = 0; I < T; ++I)
+        for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
+      }
       if constexpr (ADJ) {
         const double bb = blp[4 * kse + q], bw = bvp[4 * kse + q];
 #pragma unroll
@@ -444,6 +459,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       }
     }
   }
+  if constexpr (!CACHED) {
   // ridge on the diagonal, identity on the padding: the padded rows and
   // columns of the Gram are exactly zero, so adding 1 there gives it
   d4 dmask;   // 1 where register rr holds a diagonal entry
@@ -517,6 +533,52 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         }
         augv[I2] = a[0];
       }
+      wave_lds_sync();
+    }
+  }
+
+  // the factored tiles to the cache slot (kernel-form fit with a cache)
+  if constexpr (KF && !ADJ) {
+    if (fc) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        double2 *dst = (double2 *)(fc + (size_t)(64 * t + lane) * 4);
+        dst[0] = double2{acc[t][0], acc[t][1]};
+        dst[1] = double2{acc[t][2], acc[t][3]};
+      }
+    }
+  }
+  } else {
+    // ---- 3'. cached factor: tiles from the slot, y = L^-1 v -----------------
+    // Lane (q, c) holds L_JI^T[4rr + q][c] = L_JI[c][4rr + q] (I < J) and
+    // L_JJ^-T[4rr + q][c] = L_JJ^-1[c][4rr + q] in register rr, so each
+    // tile-vector product is a sum over the lane's four registers and then
+    // over the four rows of 16 lanes, which leaves entry c in every lane.
+    // Block J: t_J = v_J - sum_{I<J} L_JI y_I, y_J = L_JJ^-1 t_J.
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const double2 *src = (const double2 *)(fc + (size_t)(64 * t + lane) * 4);
+      const double2 a01 = src[0], a23 = src[1];
+      acc[t] = d4{a01.x, a01.y, a23.x, a23.y};
+    }
+    double *yv = L.vec;             // y, natural order
+    double *tv = L.vec + 16 * T;    // t of the current block
+#pragma unroll
+    for (int J = 0; J < T; ++J) {
+      double sp = 0.0;
+#pragma unroll
+      for (int I = 0; I < J; ++I)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) sp = fma(acc[tix<T>(J, I)][rr], yv[16 * I + 4 * rr + q], sp);
+      const double tj = quarter_bcast<0>(augv[J]) - quarter_sum(sp);
+      if (q == 0) tv[c] = tj;
+      wave_lds_sync();
+      double sy = 0.0;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) sy = fma(acc[tix<T>(J, J)][rr], tv[4 * rr + q], sy);
+      const double yj = quarter_sum(sy);
+      if (q == 0) yv[16 * J + c] = yj;
+      augv[J] = q == 0 ? yj : 0.0;
       wave_lds_sync();
     }
   }
@@ -742,7 +804,7 @@ __global__ __launch_bounds__(256, occupancy_for(T, KF)) void k_fit_batched(
     const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
     int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, double lam, double *__restrict__ tval,
-    double *__restrict__ dvec, int32_t *status) {
+    double *__restrict__ dvec, int32_t *status, double *__restrict__ fcache) {
   __shared__ WaveLds<T> lds[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
@@ -759,7 +821,8 @@ __global__ __launch_bounds__(256, occupancy_for(T, KF)) void k_fit_batched(
     if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
     return;
   }
-  fit_row<T, KF, MT>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, dvec, status, AdjIO{});
+  double *fc = KF && fcache ? fcache + (size_t)idx * (T * (T + 1) / 2) * 256 : nullptr;   // this row's cache slot
+  fit_row<T, KF, MT>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, dvec, status, AdjIO{}, fc);
 }
 
 // Adjoint of the regressions of one bucket (same rows and shapes as the fit).
@@ -769,12 +832,12 @@ constexpr int adj_occupancy_for(int T, bool KF) {
   return KF ? (T <= 2 ? 4 : (T == 3 ? 3 : (T <= 5 ? 2 : 1))) : occupancy_for(T, KF);
 }
 
-template <int T, bool KF, int MT>
+template <int T, bool KF, int MT, bool CACHED = false>
 __global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_batched(
     const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
     int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, double lam, double *__restrict__ tval,
-    AdjIO adj, int32_t *status) {
+    AdjIO adj, int32_t *status, double *__restrict__ fcache) {
   __shared__ WaveLds<T> lds[4];
   __shared__ double ebl[4][kMaxP + 8];   // epsbar (p-form, 16 kMaxT used) or b (kernel form)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -790,7 +853,9 @@ __global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_b
   wave_lds_sync();
   AdjIO aw = adj;
   aw.ebl = ebl[wave];
-  fit_row<T, KF, MT, true>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, nullptr, status, aw);
+  double *fc = CACHED ? fcache + (size_t)idx * (T * (T + 1) / 2) * 256 : nullptr;   // the fit's slot of this row
+  fit_row<T, KF, MT, true, CACHED>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, nullptr, status,
+                                   aw, fc);
 }
 
 // Adjoint of the regressions without predecessors (eps = u).
@@ -830,11 +895,12 @@ __global__ __launch_bounds__(256) void k_fit_p0(const int32_t *__restrict__ fit_
 }
 
 template <int T, bool KF, int MT>
-static void launch_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam, hipStream_t s) {
+static void launch_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam, hipStream_t s,
+                          double *fcache = nullptr) {
   if (n <= 0) return;
   hipLaunchKernelGGL((k_fit_batched<T, KF, MT>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d.blocks,
                      d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam, d.tval,
-                     d.dvec, d.status);
+                     d.dvec, d.status, fcache);
 }
 
 // p-form bucket of T tiles: the residual loops unroll 5 member tiles when
@@ -870,16 +936,17 @@ hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStrea
     // kernel form: m = N.  Without a ridge these rows (p >= N) are ENOTSPD,
     // which the p-form kernel reports before any arithmetic.
     if (lam > 0.0) {
+      double *fc = p->fcache;   // NULL: no factor cache
       phase_begin(p, ENKFMC_PH_FIT_KFORM, s);
       switch ((p->N + 15) / 16) {
-        case 1: launch_bucket<1, true, 1>(p, d, rk, nk, lam, s); break;
-        case 2: launch_bucket<2, true, 2>(p, d, rk, nk, lam, s); break;
-        case 3: launch_bucket<3, true, 3>(p, d, rk, nk, lam, s); break;
-        case 4: launch_bucket<4, true, 4>(p, d, rk, nk, lam, s); break;
-        case 5: launch_bucket<5, true, 5>(p, d, rk, nk, lam, s); break;
-        case 6: launch_bucket<6, true, 6>(p, d, rk, nk, lam, s); break;
-        case 7: launch_bucket<7, true, 7>(p, d, rk, nk, lam, s); break;
-        default: launch_bucket<8, true, 8>(p, d, rk, nk, lam, s); break;
+        case 1: launch_bucket<1, true, 1>(p, d, rk, nk, lam, s, fc); break;
+        case 2: launch_bucket<2, true, 2>(p, d, rk, nk, lam, s, fc); break;
+        case 3: launch_bucket<3, true, 3>(p, d, rk, nk, lam, s, fc); break;
+        case 4: launch_bucket<4, true, 4>(p, d, rk, nk, lam, s, fc); break;
+        case 5: launch_bucket<5, true, 5>(p, d, rk, nk, lam, s, fc); break;
+        case 6: launch_bucket<6, true, 6>(p, d, rk, nk, lam, s, fc); break;
+        case 7: launch_bucket<7, true, 7>(p, d, rk, nk, lam, s, fc); break;
+        default: launch_bucket<8, true, 8>(p, d, rk, nk, lam, s, fc); break;
       }
       phase_end(p, ENKFMC_PH_FIT_KFORM, s);
     } else {
@@ -899,13 +966,21 @@ hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStrea
   return hipGetLastError();
 }
 
-template <int T, bool KF, int MT>
+template <int T, bool KF, int MT, bool CACHED = false>
 static void launch_adj_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam,
-                              const AdjIO &adj, hipStream_t s) {
+                              const AdjIO &adj, hipStream_t s, double *fcache = nullptr) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((k_adj_regress_batched<T, KF, MT>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d.blocks,
-                     d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam, d.tval,
-                     adj, d.status);
+  hipLaunchKernelGGL((k_adj_regress_batched<T, KF, MT, CACHED>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s,
+                     d.blocks, d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam,
+                     d.tval, adj, d.status, fcache);
+}
+
+// Kernel-form adjoint of T tiles, from the fit's cached factors when it left them.
+template <int T>
+static void launch_adj_kform(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam,
+                             const AdjIO &adj, hipStream_t s) {
+  if (p->fcache_valid) launch_adj_bucket<T, true, T, true>(p, d, rows, n, lam, adj, s, p->fcache);
+  else launch_adj_bucket<T, true, T>(p, d, rows, n, lam, adj, s);
 }
 
 template <int T>
@@ -940,14 +1015,14 @@ hipError_t launch_adj_regress_batched(enkfmc_plan *p, const Dev &d, double lam, 
   if (nk > 0) {
     if (!(lam > 0.0)) return hipErrorInvalidValue;   // the fit rejects p >= N - 1 without ridge
     switch ((p->N + 15) / 16) {
-      case 1: launch_adj_bucket<1, true, 1>(p, d, rk, nk, lam, adj, s); break;
-      case 2: launch_adj_bucket<2, true, 2>(p, d, rk, nk, lam, adj, s); break;
-      case 3: launch_adj_bucket<3, true, 3>(p, d, rk, nk, lam, adj, s); break;
-      case 4: launch_adj_bucket<4, true, 4>(p, d, rk, nk, lam, adj, s); break;
-      case 5: launch_adj_bucket<5, true, 5>(p, d, rk, nk, lam, adj, s); break;
-      case 6: launch_adj_bucket<6, true, 6>(p, d, rk, nk, lam, adj, s); break;
-      case 7: launch_adj_bucket<7, true, 7>(p, d, rk, nk, lam, adj, s); break;
-      default: launch_adj_bucket<8, true, 8>(p, d, rk, nk, lam, adj, s); break;
+      case 1: launch_adj_kform<1>(p, d, rk, nk, lam, adj, s); break;
+      case 2: launch_adj_kform<2>(p, d, rk, nk, lam, adj, s); break;
+      case 3: launch_adj_kform<3>(p, d, rk, nk, lam, adj, s); break;
+      case 4: launch_adj_kform<4>(p, d, rk, nk, lam, adj, s); break;
+      case 5: launch_adj_kform<5>(p, d, rk, nk, lam, adj, s); break;
+      case 6: launch_adj_kform<6>(p, d, rk, nk, lam, adj, s); break;
+      case 7: launch_adj_kform<7>(p, d, rk, nk, lam, adj, s); break;
+      default: launch_adj_kform<8>(p, d, rk, nk, lam, adj, s); break;
     }
   }
   hipError_t e = hipGetLastError();

@@ -111,6 +111,10 @@ struct enkfmc_plan {
   int32_t timing = 0;
   int32_t async = 0;               // calls neither clear nor read the status word (enkfmc_set_async)
   int32_t an_solver = 0;           // enkfmc_solver of the last analysis
+  // kernel-form factor cache (enkfmc_plan_set_factor_cache): caller-owned
+  // device memory; valid once a batched fit with a ridge has filled it
+  double *fcache = nullptr;
+  int32_t fcache_valid = 0;
   // preconditioned CG of the local systems (ENKFMC_SOLVE_PCG)
   int32_t pcg_maxit = 2000;
   double pcg_rtol = 1e-12;

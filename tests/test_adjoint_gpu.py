@@ -68,6 +68,40 @@ def test_adjoint_matches_oracle(case, mode):
     assert e[0] <= 1e-5 and e[1] <= 1e-5 and e[2] <= 1e-5
 
 
+@pytest.mark.parametrize("case", ["kernel_form", "mixed_forms", "nonperiodic_uneven"])
+def test_factor_cache_adjoint_matches_recompute_and_oracle(case):
+    """enkfmc_plan_set_factor_cache: the batched fit keeps the kernel-form
+    rows' Cholesky tiles and the reverse pass reads them.  Equal to the
+    recomputing reverse pass up to rounding (1e-9), to the oracle within the
+    adjoint tolerance, bitwise repeatable; dropping the cache brings back the
+    recomputing pass bit for bit."""
+    p = CASES[case]()
+    res = A.analyze(p.geometry, p.Xb, p.Y, p.obs_idx, p.r_diag, p.ridge)
+    Gbar = 2.0 * (res.Xa - p.x_true[:, None])
+    dXb_o, dlogR_o, dlam_o = J.analyze_backward(p.Xb, p.obs_idx, p.r_diag, p.ridge, res, Gbar)
+    plan = Plan(p.geometry, p.N, p.obs_idx)
+    Xb = torch.as_tensor(p.Xb).cuda()
+    G = torch.as_tensor(Gbar).cuda()
+    _gpu_forward(p, plan, Xb)
+    ref = [t.cpu().numpy() for t in plan.backward(Xb, G)]
+    nbytes = plan.set_factor_cache(True)
+    _say(f"[cache] {case} n={p.n} N={p.N} cache {nbytes} bytes")
+    assert nbytes == plan.info["factor_cache_bytes"] > 0
+    _gpu_forward(p, plan, Xb)
+    got = [t.cpu().numpy() for t in plan.backward(Xb, G)]
+    again = [t.cpu().numpy() for t in plan.backward(Xb, G)]
+    e_ref = [_rel2(a, b) for a, b in zip(got, ref)]
+    e_or = [_rel2(got[0], dXb_o), _rel2(got[1], dlogR_o), abs(float(got[2]) - dlam_o) / abs(dlam_o)]
+    _say(f"[cache] {case} vs recompute {e_ref[0]:.2e} {e_ref[1]:.2e} {e_ref[2]:.2e}; "
+         f"vs oracle {e_or[0]:.2e} {e_or[1]:.2e} {e_or[2]:.2e}")
+    assert max(e_ref) <= 1e-9 and max(e_or) <= 1e-5
+    assert all(np.array_equal(a, b) for a, b in zip(got, again))
+    assert plan.set_factor_cache(False) == 0
+    _gpu_forward(p, plan, Xb)
+    back = [t.cpu().numpy() for t in plan.backward(Xb, G)]
+    assert all(np.array_equal(a, b) for a, b in zip(back, ref))
+
+
 def test_adjoint_is_bitwise_repeatable():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
