@@ -82,6 +82,56 @@ def phase_roofline(info, N, phases, xb_bytes, fit_all_flops, fit_kf_flops):
     return out
 
 
+def adjoint_roofline(info, N, counts, phases, fit_all_flops, cached=False):
+    """Achieved fraction of each phase of the reverse pass against the roof
+    that bounds it, from algorithmic counts.
+
+    adj_solve: the dual-form solve W = A^-1 Zbar, priced by the HBM bytes of
+      its two sweeps over the T tiles, F^T D V, the solve with S and the
+      assembly of W.
+    adj_factor: Dbar and betabar; FP64 flops 8 nnz N (TZ and TW, then two
+      length-N dot products per entry of T).
+    adj_regress: without the cache the regressions' Gram and Cholesky again
+      (the fit's flops) plus their passes over U_P (6 pN flops per p-form row,
+      8 pN per kernel-form row); with the cache, priced by the cached tiles it
+      must read from HBM.
+    adj_gather: Ubar tiles, the gather over sub-domains and the observation
+      terms, priced by HBM bytes."""
+    import numpy as np
+    n, nf, ml, nnz = info["n"], info["n_fit"], info["m_local"], info["nnz"]
+    tiles_b = (info["n_tiles"] + info["n_row_tiles"]) * 2048
+    fe, se = info["f_entries"], info["s_entries"]
+    p = counts.astype(np.float64)
+    passes = float(np.where(p < N, 6.0, 8.0).dot(p) * N)
+    alg = {
+        "adj_solve": ("hbm", 2 * tiles_b + n * N * 8 + 4 * nf * N * 8 + 2 * fe * 8 + se * 8 + 4 * ml * N * 8),
+        "adj_factor": ("fp64", 8.0 * nnz * N),
+        "adj_regress": (("fp64+hbm", (fit_flops(p[p < N], N) + passes, float(info["factor_cache_bytes"])))
+                        if cached else ("fp64", fit_all_flops + passes)),
+        "adj_gather": ("hbm", nnz * 8 + tiles_b + 3 * nf * N * 8 + 2 * n * N * 8),
+    }
+    out = {}
+    for ph, (bound, amount) in alg.items():
+        ms = phases.get(ph, 0.0)
+        if not ms:
+            continue
+        if bound == "fp64+hbm":
+            # p-form regressions recomputed (FP64) plus the cached kernel-form
+            # tiles read (HBM): the time both need at peak over the time taken
+            fl, by = amount
+            out[ph] = {"ms": ms, "bound": "fp64+hbm", "algorithmic_flops": fl, "algorithmic_bytes": by,
+                       "frac": (fl / PEAK_FP64 + by / PEAK_HBM) / (ms * 1e-3)}
+            continue
+        ach = amount / (ms * 1e-3)
+        if bound == "fp64":
+            out[ph] = {"ms": ms, "bound": "fp64", "algorithmic_flops": amount, "achieved": ach / 1e12,
+                       "unit": "TFLOP/s", "frac": ach / PEAK_FP64}
+        else:
+            out[ph] = {"ms": ms, "bound": "hbm", "algorithmic_bytes": amount, "achieved": ach / 1e9,
+                       "unit": "GB/s", "frac": ach / PEAK_HBM}
+    return out
+
+
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # counters, each scaled by what the same counter reads for a plain copy of
 # known size.  Valid only for the kernel source it was taken on: a changed
@@ -587,6 +637,11 @@ def main():
         roof = {"kernel": "k_fit_plain" if args.mode == "plain" else "fit", "bound": "alu",
                 "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64, "traffic": None, "fit_phase": fit_all}
+    if adjoint is not None:
+        adjoint["roofline"] = adjoint_roofline(info, prob.N, counts, adjoint["phases_ms"], flops)
+        fc = adjoint.get("factor_cache")
+        if fc is not None:
+            fc["roofline"] = adjoint_roofline(info, prob.N, counts, fc["phases_ms"], flops, cached=True)
     Xa_h = Xa.cpu().numpy()
 
     svd = None

@@ -41,10 +41,10 @@
 // Factor cache (kernel form).  Given a cache slot, the fit stores the factored
 // tiles of each kernel-form row (L_IJ^T below the diagonal, L_JJ^-T on it, as
 // step 3 leaves them in registers: NT tiles of 64 lanes x 4 doubles, each lane
-// its own 32 contiguous bytes).  The adjoint instantiated with CACHED loads
-// them instead of recomputing the Gram and the Cholesky: its loop over U_P
-// only sums eps and U_P^T b, and the bordering row's L^-1 v, which the
-// elimination would have produced, comes from a blocked forward substitution.
+// its own 32 contiguous bytes).  The kernel-form adjoint then reads them
+// instead of recomputing the Gram and the Cholesky (k_adj_kf_pre, _solve,
+// _post below): the bordering row's L^-1 v, which the elimination would have
+// produced, comes from a blocked forward substitution.
 //
 // Layout of a v_mfma_f64_16x16x4 accumulator (lane l = 16q + c, register r):
 // element (4r + q, c).  A operand: lane l holds A[c][q]; B operand: B[q][c].
@@ -244,12 +244,86 @@ __device__ __forceinline__ void adj_pre_kf(const int lane, const int64_t r, cons
   wave_lds_sync();
 }
 
-template <int T, bool KF, int MT, bool ADJ = false, bool CACHED = false>
+// Back substitution L^T x = y with the factored tiles in registers (step 4
+// of fit_row): y enters as the bordering row (entry 16J + c at lane (0, c)
+// in yr[J]) and x leaves in y[] (LDS, natural order).  Panel by panel from
+// the last: t = y_J - sum_{I>J} L_IJ^T x_I, then x_J = L_JJ^-T t.  Lane (q,
+// c) holds L_IJ^T[4rr + q][c] and L_JJ^-T[4rr + q][c] in register rr, so
+// both products multiply by the vector's entry c and sum over the row of 16
+// lanes; the four sums of a row go in one exchange (row16_sum4), which leaves
+// entry 4(c/4) + q in lane (q, c).
+template <int T>
+__device__ __forceinline__ void back_subst(const int q, const int c, const d4 (&acc)[T * (T + 1) / 2],
+                                           const double (&yr)[T], double *y) {
+  if (q == 0) {
+#pragma unroll
+    for (int J = 0; J < T; ++J) y[16 * J + c] = yr[J];
+  }
+  wave_lds_sync();
+  const int jq = 4 * (c >> 2) + q;   // the entry this lane ends up holding
+#pragma unroll
+  for (int J = T - 1; J >= 0; --J) {
+    double t = y[16 * J + jq];
+    if (J + 1 < T) {
+      double sr[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int I = J + 1; I < T; ++I) {
+        const double xc = y[16 * I + c];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) sr[rr] = fma(acc[tix<T>(I, J)][rr], xc, sr[rr]);
+      }
+      t -= row16_sum4(sr[0], sr[1], sr[2], sr[3], c);
+    }
+    wave_lds_sync();
+    if ((c & 3) == 0) y[16 * J + jq] = t;
+    wave_lds_sync();
+    const double tc = y[16 * J + c];
+    double xr[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) xr[rr] = acc[tix<T>(J, J)][rr] * tc;
+    const double x = row16_sum4(xr[0], xr[1], xr[2], xr[3], c);
+    wave_lds_sync();
+    if ((c & 3) == 0) y[16 * J + jq] = x;   // x_J overwrites t
+    wave_lds_sync();
+  }
+}
+
+// Forward substitution y = L^-1 v with the factored tiles in registers (what
+// the elimination of step 3 forms as its bordering row).  v enters at lane (0,
+// c) of vr[J] (entry 16J + c), y leaves the same way and in y[] (LDS, natural
+// order); t[] is 16 doubles of LDS scratch.  Lane (q, c) holds L_JI^T[4rr +
+// q][c] = L_JI[c][4rr + q] (I < J) and L_JJ^-T[4rr + q][c] = L_JJ^-1[c][4rr
+// + q] in register rr, so each tile-vector product is a sum over the lane's
+// registers and then over the four rows of 16 lanes, which leaves entry c in
+// every lane.  Block J: t_J = v_J - sum_{I<J} L_JI y_I, y_J = L_JJ^-1 t_J.
+template <int T>
+__device__ __forceinline__ void fwd_subst(const int q, const int c, const d4 (&acc)[T * (T + 1) / 2],
+                                          double (&vr)[T], double *y, double *t) {
+#pragma unroll
+  for (int J = 0; J < T; ++J) {
+    double sp = 0.0;
+#pragma unroll
+    for (int I = 0; I < J; ++I)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) sp = fma(acc[tix<T>(J, I)][rr], y[16 * I + 4 * rr + q], sp);
+    const double tj = quarter_bcast<0>(vr[J]) - quarter_sum(sp);
+    if (q == 0) t[c] = tj;
+    wave_lds_sync();
+    double sy = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) sy = fma(acc[tix<T>(J, J)][rr], t[4 * rr + q], sy);
+    const double yj = quarter_sum(sy);
+    if (q == 0) y[16 * J + c] = yj;
+    vr[J] = q == 0 ? yj : 0.0;
+    wave_lds_sync();
+  }
+}
+
+template <int T, bool KF, int MT, bool ADJ = false>
 __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const int p, const int N, const double mu,
                                         const double *__restrict__ U, const int ldu, const int uoff, WaveLds<T> &L,
                                         double *__restrict__ tval, const int64_t lo, double *__restrict__ dvec,
                                         int32_t *status, const AdjIO &adj, double *__restrict__ fc = nullptr) {
-  static_assert(!CACHED || (KF && ADJ), "only the kernel-form adjoint reads cached factors");
   constexpr int NT = T * (T + 1) / 2;
   const int q = lane >> 4, c = lane & 15;
   const int m = KF ? N : p;
@@ -295,12 +369,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
       for (int I = 0; I < T; ++I) fb[I] = U[offb + 16 * I];
       __builtin_amdgcn_sched_barrier(0);   // keep each half's loads ahead of the other half's products
-      if constexpr (!CACHED) {
 #pragma unroll
-        for (int I = 0; I < T; ++I)
+      for (int I = 0; I < T; ++I)
 #pragma unroll
-          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
-      }
+        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
       if constexpr (ADJ) {
         const double bb = blp[4 * ks + q], bw = bvp[4 * ks + q];
 #pragma unroll
@@ -314,12 +386,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
 #pragma unroll
       for (int I = 0; I < T; ++I) fa[I] = U[offa + 16 * I];
       __builtin_amdgcn_sched_barrier(0);
-      if constexpr (!CACHED) {
 #pragma unroll
-        for (int I = 0; I < T; ++I)
+      for (int I = 0; I < T; ++I)
 #pragma unroll
-          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fb[J], fb[I], acc[tix<T>(I, J)]);
-      }
+        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fb[J], fb[I], acc[tix<T>(I, J)]);
       if constexpr (ADJ) {
         const double bb = blp[4 * ks + 4 + q], bw = bvp[4 * ks + 4 + q];
 #pragma unroll
@@ -331,12 +401,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       __builtin_amdgcn_sched_barrier(0);
     }
     if (ksn & 1) {   // the last prefetch holds k-step ksn - 1
-      if constexpr (!CACHED) {
 #pragma unroll
-        for (int I = 0; I < T; ++I)
+      for (int I = 0; I < T; ++I)
 #pragma unroll
-          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
-      }
+        for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(fa[J], fa[I], acc[tix<T>(I, J)]);
       if constexpr (ADJ) {
         const double bb = blp[4 * kse + q], bw = bvp[4 * kse + q];
 #pragma unroll
@@ -459,7 +527,6 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       }
     }
   }
-  if constexpr (!CACHED) {
   // ridge on the diagonal, identity on the padding: the padded rows and
   // columns of the Gram are exactly zero, so adding 1 there gives it
   d4 dmask;   // 1 where register rr holds a diagonal entry
@@ -548,80 +615,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       }
     }
   }
-  } else {
-    // ---- 3'. cached factor: tiles from the slot, y = L^-1 v -----------------
-    // Lane (q, c) holds L_JI^T[4rr + q][c] = L_JI[c][4rr + q] (I < J) and
-    // L_JJ^-T[4rr + q][c] = L_JJ^-1[c][4rr + q] in register rr, so each
-    // tile-vector product is a sum over the lane's four registers and then
-    // over the four rows of 16 lanes, which leaves entry c in every lane.
-    // Block J: t_J = v_J - sum_{I<J} L_JI y_I, y_J = L_JJ^-1 t_J.
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const double2 *src = (const double2 *)(fc + (size_t)(64 * t + lane) * 4);
-      const double2 a01 = src[0], a23 = src[1];
-      acc[t] = d4{a01.x, a01.y, a23.x, a23.y};
-    }
-    double *yv = L.vec;             // y, natural order
-    double *tv = L.vec + 16 * T;    // t of the current block
-#pragma unroll
-    for (int J = 0; J < T; ++J) {
-      double sp = 0.0;
-#pragma unroll
-      for (int I = 0; I < J; ++I)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) sp = fma(acc[tix<T>(J, I)][rr], yv[16 * I + 4 * rr + q], sp);
-      const double tj = quarter_bcast<0>(augv[J]) - quarter_sum(sp);
-      if (q == 0) tv[c] = tj;
-      wave_lds_sync();
-      double sy = 0.0;
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr) sy = fma(acc[tix<T>(J, J)][rr], tv[4 * rr + q], sy);
-      const double yj = quarter_sum(sy);
-      if (q == 0) yv[16 * J + c] = yj;
-      augv[J] = q == 0 ? yj : 0.0;
-      wave_lds_sync();
-    }
-  }
 
   // ---- 4. back substitution L^T x = y (y = the factored bordering row) ----
-  // Panel by panel from the last: t = y_J - sum_{I>J} L_IJ^T x_I, then
-  // x_J = L_JJ^-T t.  Lane (q, c) holds L_IJ^T[4rr + q][c] and
-  // L_JJ^-T[4rr + q][c] in register rr, so both products multiply by the
-  // vector's entry c and sum over the row of 16 lanes; the four sums of a row
-  // go in one exchange (row16_sum4), which leaves entry 4(c/4) + q in lane
-  // (q, c).  y (then x) stays in LDS in natural order.
-  double *y = L.vec;
-  if (q == 0) {
-#pragma unroll
-    for (int J = 0; J < T; ++J) y[16 * J + c] = augv[J];
-  }
-  wave_lds_sync();
-  const int jq = 4 * (c >> 2) + q;   // the entry this lane ends up holding
-#pragma unroll
-  for (int J = T - 1; J >= 0; --J) {
-    double t = y[16 * J + jq];
-    if (J + 1 < T) {
-      double sr[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int I = J + 1; I < T; ++I) {
-        const double xc = y[16 * I + c];
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) sr[rr] = fma(acc[tix<T>(I, J)][rr], xc, sr[rr]);
-      }
-      t -= row16_sum4(sr[0], sr[1], sr[2], sr[3], c);
-    }
-    wave_lds_sync();
-    if ((c & 3) == 0) y[16 * J + jq] = t;
-    wave_lds_sync();
-    const double tc = y[16 * J + c];
-    double xr[4];
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) xr[rr] = acc[tix<T>(J, J)][rr] * tc;
-    const double x = row16_sum4(xr[0], xr[1], xr[2], xr[3], c);
-    wave_lds_sync();
-    if ((c & 3) == 0) y[16 * J + jq] = x;   // x_J overwrites t
-    wave_lds_sync();
-  }
+  double *y = L.vec;   // x, natural order
+  back_subst<T>(q, c, acc, augv, y);
 
   if constexpr (!ADJ) {
   // ---- 5. coefficients and residual variance --------------------------------
@@ -711,17 +708,18 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         gacc[I] = 0.0;
       }
       // four k-steps of fragment loads at a time (pad row past the last)
-      const int ks4 = (((p + 3) >> 2) + 3) & ~3;
-      for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
-        double f[4][T];
+      constexpr int kB = 4;
+      const int ksb = (((p + 3) >> 2) + kB - 1) & ~(kB - 1);
+      for (int ks0 = 0; ks0 < ksb; ks0 += kB) {
+        double f[kB][T];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kB; ++u) {
           const int off = L.pidx[4 * (ks0 + u) + q] * ldu + c;
 #pragma unroll
           for (int I = 0; I < T; ++I) f[u][I] = U[off + 16 * I];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kB; ++u) {
           const int a = 4 * (ks0 + u) + q;
           double b = 0.0;
 #pragma unroll
@@ -832,12 +830,12 @@ constexpr int adj_occupancy_for(int T, bool KF) {
   return KF ? (T <= 2 ? 4 : (T == 3 ? 3 : (T <= 5 ? 2 : 1))) : occupancy_for(T, KF);
 }
 
-template <int T, bool KF, int MT, bool CACHED = false>
+template <int T, bool KF, int MT>
 __global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_batched(
     const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
     int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, double lam, double *__restrict__ tval,
-    AdjIO adj, int32_t *status, double *__restrict__ fcache) {
+    AdjIO adj, int32_t *status) {
   __shared__ WaveLds<T> lds[4];
   __shared__ double ebl[4][kMaxP + 8];   // epsbar (p-form, 16 kMaxT used) or b (kernel form)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -853,9 +851,189 @@ __global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_b
   wave_lds_sync();
   AdjIO aw = adj;
   aw.ebl = ebl[wave];
-  double *fc = CACHED ? fcache + (size_t)idx * (T * (T + 1) / 2) * 256 : nullptr;   // the fit's slot of this row
-  fit_row<T, KF, MT, true, CACHED>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, nullptr, status,
-                                   aw, fc);
+  fit_row<T, KF, MT, true>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, nullptr, status, aw);
+}
+
+// ---- kernel-form adjoint from the cached factor, in three launches ---------
+// The recomputing adjoint (fit_row in ADJ mode) holds the Gram tiles in
+// registers through its passes over U_P, at one or two wavefronts per SIMD,
+// and those passes wait on their loads.  With the factor cached, the passes
+// need no tiles and run as kernels of their own at high residency; only the
+// solve holds the tiles, and it streams them from HBM once.
+//   k_adj_kf_pre:   beta and b (push-through, as in adj_pre_kf), the sums
+//                   eps = u - U_P^T beta and v = U_P^T b; writes e1, epsbar
+//                   (into e2) and v (into vbuf);
+//   k_adj_kf_solve: the row's tiles from the cache, y = L^-1 v, x = L^-T y
+//                   (x overwrites v in vbuf);
+//   k_adj_kf_post:  s = (N-1)/mu (b - U_P x) (into sb), the row's share of
+//                   dL/dlam, g = U_P^T s, e2 = -(g/(N-1) + epsbar).
+// vbuf holds N doubles per fit row (row r at r N).
+
+// Predecessor rows of fit row r into pidx (the pad row past p).
+__device__ __forceinline__ void load_pidx(const int lane, const int64_t r, const Block *__restrict__ blocks,
+                                          const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
+                                          const int32_t *__restrict__ col, const int64_t lo, const int p,
+                                          const int zrow, int *pidx) {
+  const Block B = blocks[fit_blk[r]];
+  for (int k = lane; k < kMaxP + 8; k += 64) pidx[k] = k < p ? fit_glob[B.row0 + col[lo + k]] : zrow;
+  wave_lds_sync();
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_adj_kf_pre(
+    const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
+    int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, double lam, const double *__restrict__ tval,
+    AdjIO adj, double *__restrict__ vbuf) {
+  __shared__ int spidx[4][kMaxP + 8];
+  __shared__ double sbeta[4][kMaxP + 8], sb[4][kMaxP + 8];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+  const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
+  if (idx >= nrows) return;
+  const int64_t r = rows[idx];
+  const int64_t lo = row_ptr[r];
+  const int p = (int)(row_ptr[r + 1] - lo);
+  const int uoff = fit_glob[r] * ldu;
+  int *pidx = spidx[wave];
+  double *bl = sbeta[wave], *bv = sb[wave];
+  const double nm1 = (double)(N - 1), mu = lam * nm1, Db = adj.dbar[r];
+  const double coef = 2.0 * Db * mu / nm1;
+  for (int a = lane; a < kMaxP + 8; a += 64) {
+    const double beta = a < p ? -tval[lo + a] : 0.0;
+    const double b = a < p ? fma(-coef, beta, adj.sb[lo + a]) : 0.0;
+    bl[a] = beta;
+    bv[a] = b;
+    if (a < p) adj.sb[lo + a] = b;
+  }
+  load_pidx(lane, r, blocks, fit_glob, fit_blk, col, lo, p, zrow, pidx);
+  // lane (q, c) sums beta_a U[P_a][k] and b_a U[P_a][k] over predecessors
+  // a = 4ks + q for members k = 16I + c, four k-steps of loads per trip
+  // (past p: the zero pad row, beta = b = 0; 4 * 48 <= kMaxP)
+  double ea[T], ta[T];
+#pragma unroll
+  for (int I = 0; I < T; ++I) ea[I] = ta[I] = 0.0;
+  const int ks4 = (((p + 3) >> 2) + 3) & ~3;
+  for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
+    double f[4][T];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int off = pidx[4 * (ks0 + u) + q] * ldu + c;
+#pragma unroll
+      for (int I = 0; I < T; ++I) f[u][I] = U[off + 16 * I];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double bb = bl[4 * (ks0 + u) + q], bw = bv[4 * (ks0 + u) + q];
+#pragma unroll
+      for (int I = 0; I < T; ++I) {
+        ea[I] = fma(bb, f[u][I], ea[I]);
+        ta[I] = fma(bw, f[u][I], ta[I]);
+      }
+    }
+  }
+#pragma unroll
+  for (int I = 0; I < T; ++I) {
+    const double es = quarter_sum(ea[I]);
+    const double tb = quarter_sum(ta[I]);
+    const int k = 16 * I + c;
+    if (q == 0 && k < N) {
+      const double eps = U[uoff + k] - es;
+      adj.e1[r * N + k] = eps / nm1;
+      adj.e2[r * N + k] = 2.0 * Db * eps / nm1;
+      vbuf[r * N + k] = tb;
+    }
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(256, adj_occupancy_for(T, true)) void k_adj_kf_solve(
+    const int32_t *__restrict__ rows, int64_t nrows, int N, const double *__restrict__ fcache,
+    double *__restrict__ vbuf) {
+  constexpr int NT = T * (T + 1) / 2;
+  __shared__ double svec[4][16 * (T + 1)];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+  const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
+  if (idx >= nrows) return;
+  const int64_t r = rows[idx];
+  const double *fc = fcache + (size_t)idx * NT * 256;   // the fit's slot of this row
+  d4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const double2 *src = (const double2 *)(fc + (size_t)(64 * t + lane) * 4);
+    const double2 a01 = src[0], a23 = src[1];
+    acc[t] = d4{a01.x, a01.y, a23.x, a23.y};
+  }
+  double vr[T];
+#pragma unroll
+  for (int J = 0; J < T; ++J) vr[J] = (q == 0 && 16 * J + c < N) ? vbuf[r * N + 16 * J + c] : 0.0;
+  double *y = svec[wave];
+  fwd_subst<T>(q, c, acc, vr, y, y + 16 * T);
+  back_subst<T>(q, c, acc, vr, y);
+  for (int k = lane; k < N; k += 64) vbuf[r * N + k] = y[k];
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_adj_kf_post(
+    const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
+    int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, double lam, const double *__restrict__ tval,
+    AdjIO adj, const double *__restrict__ vbuf) {
+  __shared__ int spidx[4][kMaxP + 8];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+  const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
+  if (idx >= nrows) return;
+  const int64_t r = rows[idx];
+  const int64_t lo = row_ptr[r];
+  const int p = (int)(row_ptr[r + 1] - lo);
+  int *pidx = spidx[wave];
+  load_pidx(lane, r, blocks, fit_glob, fit_blk, col, lo, p, zrow, pidx);
+  const double nm1 = (double)(N - 1), mu = lam * nm1;
+  // s_a = (N-1)/mu (b_a - sum_k U[P_a][k] x_k) and g = U_P^T s from the same
+  // fragments: lane (q, c) loads members 16I + c of predecessor 4ks + q, and
+  // the 16 lanes of each quarter add their partial sums
+  double wv[T], gacc[T];
+#pragma unroll
+  for (int I = 0; I < T; ++I) {
+    wv[I] = 16 * I + c < N ? vbuf[r * N + 16 * I + c] : 0.0;
+    gacc[I] = 0.0;
+  }
+  double ls = 0.0;
+  const int ks4 = (((p + 3) >> 2) + 3) & ~3;
+  for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
+    double f[4][T], sbv[4], tv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int a = 4 * (ks0 + u) + q;
+      const int off = pidx[a] * ldu + c;
+#pragma unroll
+      for (int I = 0; I < T; ++I) f[u][I] = U[off + 16 * I];
+      sbv[u] = a < p ? adj.sb[lo + a] : 0.0;
+      tv[u] = a < p ? tval[lo + a] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int a = 4 * (ks0 + u) + q;
+      double b = 0.0;
+#pragma unroll
+      for (int I = 0; I < T; ++I) b = fma(f[u][I], wv[I], b);
+      b = row16_sum(b);
+      const double sv = a < p ? (nm1 / mu) * (sbv[u] - b) : 0.0;
+      if (c == 0 && a < p) {
+        adj.sb[lo + a] = sv;
+        ls = fma(sv, tv[u], ls);
+      }
+#pragma unroll
+      for (int I = 0; I < T; ++I) gacc[I] = fma(f[u][I], sv, gacc[I]);
+    }
+  }
+#pragma unroll
+  for (int I = 0; I < T; ++I) {
+    const double e = quarter_sum(gacc[I]);
+    const int k = 16 * I + c;
+    if (q == 0 && k < N) adj.e2[r * N + k] = -(e / nm1 + adj.e2[r * N + k]);
+  }
+  ls = wave_sum(ls);
+  if (lane == 0) adj.lam_row[r] = ls;
 }
 
 // Adjoint of the regressions without predecessors (eps = u).
@@ -966,21 +1144,29 @@ hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStrea
   return hipGetLastError();
 }
 
-template <int T, bool KF, int MT, bool CACHED = false>
+template <int T, bool KF, int MT>
 static void launch_adj_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam,
-                              const AdjIO &adj, hipStream_t s, double *fcache = nullptr) {
+                              const AdjIO &adj, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((k_adj_regress_batched<T, KF, MT, CACHED>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s,
-                     d.blocks, d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam,
-                     d.tval, adj, d.status, fcache);
+  hipLaunchKernelGGL((k_adj_regress_batched<T, KF, MT>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d.blocks,
+                     d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam, d.tval,
+                     adj, d.status);
 }
 
 // Kernel-form adjoint of T tiles, from the fit's cached factors when it left them.
 template <int T>
 static void launch_adj_kform(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam,
                              const AdjIO &adj, hipStream_t s) {
-  if (p->fcache_valid) launch_adj_bucket<T, true, T, true>(p, d, rows, n, lam, adj, s, p->fcache);
-  else launch_adj_bucket<T, true, T>(p, d, rows, n, lam, adj, s);
+  if (n <= 0) return;
+  if (!p->fcache_valid) return launch_adj_bucket<T, true, T>(p, d, rows, n, lam, adj, s);
+  // the cached factor: two passes over U_P and the solve between them, with
+  // v and then x in the Ubar buffer (not in use until the gather)
+  const dim3 g((unsigned)((n + 3) / 4));
+  hipLaunchKernelGGL(k_adj_kf_pre<T>, g, dim3(256), 0, s, d.blocks, d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U,
+                     p->ldu, p->N, rows, n, (int)p->n, lam, d.tval, adj, d.ubar);
+  hipLaunchKernelGGL(k_adj_kf_solve<T>, g, dim3(256), 0, s, rows, n, p->N, (const double *)p->fcache, d.ubar);
+  hipLaunchKernelGGL(k_adj_kf_post<T>, g, dim3(256), 0, s, d.blocks, d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U,
+                     p->ldu, p->N, rows, n, (int)p->n, lam, d.tval, adj, (const double *)d.ubar);
 }
 
 template <int T>
