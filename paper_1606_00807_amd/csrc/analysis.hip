@@ -24,7 +24,6 @@
 
 namespace enkfmc {
 
-typedef double d2 __attribute__((ext_vector_type(2)));
 
 // Dense tiles T_RC (row-major) of row tile R, and the inverse of T_RR.
 // One wavefront per (block, row tile).  The CSR entries of the tile's 16 rows

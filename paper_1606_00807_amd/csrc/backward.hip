@@ -148,15 +148,21 @@ __global__ __launch_bounds__(64) void k_adj_solve_S(const Block *__restrict__ bl
 // sum_C T_RC Z_C and TW_R likewise (C over the pattern's tiles of R, the
 // strictly lower T_RR included), over the wave's 16 members, accumulated
 // transposed: with the operands of each v_mfma_f64_16x16x4 swapped, the
-// accumulator holds (TZ_R)^T, so lane (q, c) keeps row c of TZ_R and TW_R at
-// members 16g + 4r + q -- exactly the A operands the 16 x 16 products below
-// need, so they stay in registers (scaled by 1/d_c).
+// accumulator holds (TZ_R)^T, so lane (q, c) keeps row c of TZ_R and TW_R --
+// exactly the A operands the 16 x 16 products below need, so they stay in
+// registers (scaled by 1/d_c).
 // Dbar_i = (TW)_i . (TZ)_i / d_i^2: each wave sums its members, the partials
 // meet in LDS and are added in member-tile order.  Then per tile (R, C) of the
 // pattern each wave forms its members' share of (TZ_R/d) W_C^T + (TW_R/d)
 // Z_C^T; the shares are added in LDS in member-tile order, and the entries in
 // the pattern of T are betabar, written in CSR order.
-template <int G>
+// Member order: register r of lane (q, c) holds member 16g + 4q + r (the A
+// operand of pass 1 takes member 16g + pi(c), pi(4r + q) = 4q + r), and
+// k-step kc of pass 1 takes row 4q + kc of the tile.  Every lane then loads
+// four consecutive doubles of a row (T_RC in pass 1, W_C and Z_C in pass 2):
+// with WIDE (N a multiple of 4, rows 32-byte aligned) as two 16-byte loads,
+// which touch half the cache lines of four 8-byte ones spread over 16 rows.
+template <int G, bool WIDE>
 __global__ __launch_bounds__(64 * G) void k_adj_factor_tiles(const Block *__restrict__ blocks,
                                                              const int64_t *__restrict__ row_ptr,
                                                              const int32_t *__restrict__ col,
@@ -189,27 +195,46 @@ __global__ __launch_bounds__(64 * G) void k_adj_factor_tiles(const Block *__rest
     srow[0][tid] = row < B.n ? row_ptr[B.row0 + row] : 0;
     srow[1][tid] = row < B.n ? row_ptr[B.row0 + row + 1] : 0;
   }
-  const int mc = 16 * g + c;                     // member of this lane's A operands below
-  const bool mok = mc < N;
-  d4 az, aw;
-  // identity part: (Z_R)^T at lane (q, c), register r: Z[16R + c][16g + 4r + q]
+  const int mq = 16 * g + 4 * q;                 // members mq .. mq + 3 of this lane's registers
+  // four consecutive doubles of a row at members mq..mq+3 (zero past N or past the block)
+  auto row4 = [&](const double *base, int row, bool rin, double (&v)[4]) {
+    if constexpr (WIDE) {
+      if (rin && mq < N) {
+        const d2 *p2 = (const d2 *)(base + (int64_t)row * N + mq);
+        const d2 lo = p2[0], hi = p2[1];
+        v[0] = lo[0]; v[1] = lo[1]; v[2] = hi[0]; v[3] = hi[1];
+      } else {
+        v[0] = v[1] = v[2] = v[3] = 0.0;
+      }
+    } else {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int m = 16 * g + 4 * r + q;
-    const bool in = rowc < B.n && m < N;
-    az[r] = in ? Zb[(int64_t)rowc * N + m] : 0.0;
-    aw[r] = in ? Wb[(int64_t)rowc * N + m] : 0.0;
+      for (int r = 0; r < 4; ++r) v[r] = rin && mq + r < N ? base[(int64_t)row * N + mq + r] : 0.0;
+    }
+  };
+  d4 az, aw;
+  {
+    // identity part: (Z_R)^T at lane (q, c), register r: Z[16R + c][16g + 4q + r]
+    double zr[4], wr[4];
+    row4(Zb, rowc, rowc < B.n, zr);
+    row4(Wb, rowc, rowc < B.n, wr);
+    az = d4{zr[0], zr[1], zr[2], zr[3]};
+    aw = d4{wr[0], wr[1], wr[2], wr[3]};
   }
+  const int mp = 16 * g + 4 * (c & 3) + (c >> 2);   // member of this lane's A operands in pass 1
+  const bool mpok = mp < N;
   for (int t = 0; t <= nt; ++t) {                // t == nt: the diagonal tile
     const int C = t < nt ? rt_col[t0 + t] : R;
     const double *Tt = t < nt ? tiles + (int64_t)rt_slot[t0 + t] * 256 : tdiag + rt * 256;
+    // B operand of k-step kc: T_RC^T[4q + kc][c] = T_RC[c][4q + kc]
+    const d2 *t2 = (const d2 *)(Tt + c * 16 + 4 * q);
+    const d2 tlo = t2[0], thi = t2[1];
+    const double tb[4] = {tlo[0], tlo[1], thi[0], thi[1]};
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
-      const double tb = Tt[c * 16 + 4 * kc + q];   // B operand: T_RC^T[4kc + q][c]
-      const int zr = 16 * C + 4 * kc + q;          // A operand: Z_C^T[mc][4kc + q]
-      const bool in = zr < B.n && mok;
-      az = mfma64(in ? Zb[(int64_t)zr * N + mc] : 0.0, tb, az);
-      aw = mfma64(in ? Wb[(int64_t)zr * N + mc] : 0.0, tb, aw);
+      const int zr = 16 * C + 4 * q + kc;          // A operand: Z_C^T[mp][4q + kc]
+      const bool in = zr < B.n && mpok;
+      az = mfma64(in ? Zb[(int64_t)zr * N + mp] : 0.0, tb[kc], az);
+      aw = mfma64(in ? Wb[(int64_t)zr * N + mp] : 0.0, tb[kc], aw);
     }
   }
   double dp = 0.0;
@@ -232,16 +257,14 @@ __global__ __launch_bounds__(64 * G) void k_adj_factor_tiles(const Block *__rest
   for (int t = 0; t <= nt; ++t) {
     const int C = t < nt ? rt_col[t0 + t] : R;
     const int jr = 16 * C + c;                   // row of W_C, Z_C for the B operand
-    const bool jin = jr < B.n;
+    double bw[4], bz[4];                         // k-step r: member 16g + 4q + r
+    row4(Wb, jr, jr < B.n, bw);
+    row4(Zb, jr, jr < B.n, bz);
     d4 o1 = d4{0.0, 0.0, 0.0, 0.0}, o2 = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int k = 16 * g + 4 * r + q;          // k-step r: members 16g + 4r + q
-      const bool in = jin && k < N;
-      const double bw = in ? Wb[(int64_t)jr * N + k] : 0.0;
-      const double bz = in ? Zb[(int64_t)jr * N + k] : 0.0;
-      o1 = mfma64(az[r], bw, o1);
-      o2 = mfma64(aw[r], bz, o2);
+      o1 = mfma64(az[r], bw[r], o1);
+      o2 = mfma64(aw[r], bz[r], o2);
     }
     const d4 o = o1 + o2;
     double *so = sred[t & 1][g];
@@ -687,10 +710,17 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   phase_begin(p, ENKFMC_PH_ADJ_FACTOR, s);
   {
     const int mt = max_block_tiles(p);
-#define ADJ_FACTOR(G)                                                                                           \
-  hipLaunchKernelGGL(k_adj_factor_tiles<G>, dim3(nb * (unsigned)mt), dim3(64 * G), 0, s, d.blocks, d.row_ptr, d.col, \
-                     d.rt_ptr, d.rt_col, d.rt_slot, d.tile_eoff, d.tiles, d.tdiag, d.dvec, d.Z, d.W, N, mt, d.dbar, \
-                     d.aux3)
+#define ADJ_FACTOR(G)                                                                                            \
+  do {                                                                                                           \
+    if (N % 4 == 0)                                                                                              \
+      hipLaunchKernelGGL((k_adj_factor_tiles<G, true>), dim3(nb * (unsigned)mt), dim3(64 * G), 0, s, d.blocks,    \
+                         d.row_ptr, d.col, d.rt_ptr, d.rt_col, d.rt_slot, d.tile_eoff, d.tiles, d.tdiag, d.dvec, d.Z, \
+                         d.W, N, mt, d.dbar, d.aux3);                                                            \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_adj_factor_tiles<G, false>), dim3(nb * (unsigned)mt), dim3(64 * G), 0, s, d.blocks,   \
+                         d.row_ptr, d.col, d.rt_ptr, d.rt_col, d.rt_slot, d.tile_eoff, d.tiles, d.tdiag, d.dvec, d.Z, \
+                         d.W, N, mt, d.dbar, d.aux3);                                                            \
+  } while (0)
     switch ((N + 15) / 16) {   // member tiles kept in registers (N <= 128)
       case 1: ADJ_FACTOR(1); break;
       case 2: ADJ_FACTOR(2); break;

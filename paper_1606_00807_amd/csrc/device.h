@@ -83,6 +83,7 @@ inline Dev make_dev(enkfmc_plan *p) {
 // holds element (4r + q, c) in register r; the A operand of a product is
 // A[c][q] at lane (q, c), the B operand B[q][c].
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 __device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
