@@ -487,29 +487,43 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
         }
       }
     } else {
-      for (int ks = 0; ks < ksteps; ++ks) {
-        double f[T];
+      // one 16-byte load per tile brings members 8ks + 2q and 8ks + 2q + 1,
+      // two k-steps of the products (as in the fit above); 8 * ks2 <= ldu
+      const int ks2 = (N + 7) >> 3;
+      const double nm1 = (double)(N - 1);
+      for (int ks = 0; ks < ks2; ++ks) {
+        double2 f[T];
 #pragma unroll
-        for (int I = 0; I < T; ++I) f[I] = U[base[I] + 4 * ks];
-        const int k = 4 * ks + q;
-        const double uk = U[uoff + k];
-        double es = 0.0;
+        for (int I = 0; I < T; ++I) f[I] = *(const double2 *)&U[base[I] + q + 8 * ks];
+        const double2 uk = *(const double2 *)&U[uoff + 2 * q + 8 * ks];
+        double es0 = 0.0, es1 = 0.0;
 #pragma unroll
         for (int I = 0; I < T; ++I) {
 #pragma unroll
-          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[J], f[I], acc[tix<T>(I, J)]);
-          es = fma(bet[I], f[I], es);
-        }
-        es = row16_sum(es);
-        const double nm1 = (double)(N - 1);
-        const double eps = k < N ? uk - es : 0.0;
-        const double eb = 2.0 * Db * eps / nm1;
-        if (c == 0 && k < N) {
-          adj.e1[r * N + k] = eps / nm1;
-          adj.ebl[k] = eb;
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[J].x, f[I].x, acc[tix<T>(I, J)]);
+          es0 = fma(bet[I], f[I].x, es0);
         }
 #pragma unroll
-        for (int I = 0; I < T; ++I) vp[I] = fma(f[I], eb, vp[I]);
+        for (int I = 0; I < T; ++I) {
+#pragma unroll
+          for (int J = 0; J <= I; ++J) acc[tix<T>(I, J)] = mfma64(f[J].y, f[I].y, acc[tix<T>(I, J)]);
+          es1 = fma(bet[I], f[I].y, es1);
+        }
+        es0 = row16_sum(es0);
+        es1 = row16_sum(es1);
+        const int k0 = 8 * ks + 2 * q, k1 = k0 + 1;
+        const double eps0 = k0 < N ? uk.x - es0 : 0.0, eps1 = k1 < N ? uk.y - es1 : 0.0;
+        const double eb0 = 2.0 * Db * eps0 / nm1, eb1 = 2.0 * Db * eps1 / nm1;
+        if (c == 0 && k0 < N) {
+          adj.e1[r * N + k0] = eps0 / nm1;
+          adj.ebl[k0] = eb0;
+        }
+        if (c == 0 && k1 < N) {
+          adj.e1[r * N + k1] = eps1 / nm1;
+          adj.ebl[k1] = eb1;
+        }
+#pragma unroll
+        for (int I = 0; I < T; ++I) vp[I] = fma(f[I].y, eb1, fma(f[I].x, eb0, vp[I]));
       }
     }
     if constexpr (ADJ) {
