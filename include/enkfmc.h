@@ -109,8 +109,7 @@ typedef struct {
   int64_t n_tiles;         /* stored off-diagonal 16x16 tiles of T                   */
   int64_t f_entries;       /* entries of the dual form's F = T^-T H^T, all blocks     */
   int64_t s_entries;       /* entries of its S = R + F^T D F, all blocks              */
-  size_t factor_cache_bytes; /* memory enkfmc_plan_set_factor_cache needs (0: no
-                              * kernel-form regressions)                             */
+  size_t factor_cache_bytes; /* memory enkfmc_plan_set_factor_cache needs      */
 } enkfmc_plan_info;
 
 /* Build the decomposition of Section 3 (host only, no device work).
@@ -127,17 +126,18 @@ enkfmc_status enkfmc_plan_get_info(const enkfmc_plan *p, enkfmc_plan_info *info)
  * given another workspace. */
 enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes, void *stream);
 
-/* Optional cache of the kernel-form regressions' factors (rows with p >= N
- * under a ridge, eq. 1 solved through its N x N kernel system), for the
- * reverse pass.  dev: caller-owned device memory of at least
- * info.factor_cache_bytes (256-byte aligned; T(T + 1)/2 x 2 KiB per such row,
- * T = ceil(N/16): 30 KiB at N = 80), or NULL to drop the cache.  While set,
- * every ENKFMC_FIT_BATCHED fit with ridge > 0 writes each kernel-form row's
- * Cholesky tiles there, and enkfmc_analyze_backward after that fit reads them
- * instead of recomputing the row's Gram and Cholesky.  The result differs
- * from the recomputing reverse pass only by rounding.  The plan keeps the
- * pointer; setting or dropping the cache invalidates what it holds until the
- * next fit.  Errors: EINVAL (NULL plan, misaligned), ENOMEM (too small). */
+/* Optional cache of the regressions' Cholesky factors (eq. 1, each solved as
+ * a p x p system, or as its N x N kernel system when p >= N) for the reverse
+ * pass.  dev: caller-owned device memory of at least info.factor_cache_bytes
+ * (256-byte aligned; T(T + 1)/2 x 2 KiB per regression of the one-wavefront
+ * kernels with predecessors, T = ceil(min(p, N)/16): 30 KiB at p or N = 80),
+ * or NULL to drop the cache.  While set, every ENKFMC_FIT_BATCHED fit writes
+ * each such row's factored tiles there, and enkfmc_analyze_backward after
+ * that fit reads them instead of recomputing the row's Gram and Cholesky.
+ * The result differs from the recomputing reverse pass only by rounding.
+ * The plan keeps the pointer; setting or dropping the cache invalidates what
+ * it holds until the next fit.  Errors: EINVAL (NULL plan, misaligned),
+ * ENOMEM (too small). */
 enkfmc_status enkfmc_plan_set_factor_cache(enkfmc_plan *p, void *dev, size_t bytes);
 
 /* Fit B^-1 = T^T D^-1 T in every sub-domain (eq. 1, eq. 8; Alg. 3 first step).

@@ -166,10 +166,10 @@ class Plan:
         return self.workspace
 
     def set_factor_cache(self, enable: bool = True) -> int:
-        """Keep the kernel-form regressions' Cholesky tiles from each batched
-        fit (with a ridge) in device memory owned by this object, so that the
-        reverse pass reads them instead of recomputing each row's Gram and
-        factorisation.  Returns the bytes held (0 when disabled)."""
+        """Keep the regressions' Cholesky tiles from each batched fit in
+        device memory owned by this object, so that the reverse pass reads
+        them instead of recomputing each row's Gram and factorisation.
+        Returns the bytes held (0 when disabled)."""
         import torch
         check(self.lib.enkfmc_plan_set_factor_cache(self._h, None, ctypes.c_size_t(0)))
         self._factor_cache = None

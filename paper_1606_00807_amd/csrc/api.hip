@@ -76,13 +76,9 @@ static enkfmc_status finish(enkfmc_plan *p, hipStream_t s, const char *what) {
   return decode_status(st, what);
 }
 
-// Bytes of the kernel-form factor cache: the factored tiles of every row of
-// the kernel-form bucket, T(T + 1)/2 tiles of 256 doubles each, T = ceil(N/16).
-static size_t factor_cache_bytes(const enkfmc_plan *p) {
-  const int64_t nk = p->bucket_off[kBucketKF + 1] - p->bucket_off[kBucketKF];
-  const size_t T = (size_t)(p->N + 15) / 16;
-  return (size_t)nk * (T * (T + 1) / 2) * 256 * sizeof(double);
-}
+// Bytes of the factor cache: the factored tiles of every row of the
+// one-wavefront buckets (layout in plan.h).
+static size_t factor_cache_bytes(const enkfmc_plan *p) { return fcache_offset(p, kBucketKF + 1) * sizeof(double); }
 
 static enkfmc_status begin(enkfmc_plan *p, hipStream_t s, const char *what) {
   if (!p->ws) return fail(ENKFMC_ESTATE, std::string(what) + ": no workspace (call enkfmc_plan_set_workspace)");
@@ -244,7 +240,7 @@ enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t 
   st = finish(p, s, "fit");
   if (st != ENKFMC_OK) return st;
   p->fitted = 1;
-  p->fcache_valid = mode == ENKFMC_FIT_BATCHED && ridge > 0.0 && p->fcache != nullptr;
+  p->fcache_valid = mode == ENKFMC_FIT_BATCHED && p->fcache != nullptr;
   p->fit_mode = mode;
   p->fit_ridge = ridge;
   p->fit_xb = Xb;

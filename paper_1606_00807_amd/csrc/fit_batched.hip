@@ -618,8 +618,8 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
     }
   }
 
-  // the factored tiles to the cache slot (kernel-form fit with a cache)
-  if constexpr (KF && !ADJ) {
+  // the factored tiles to the cache slot (fit with a factor cache)
+  if constexpr (!ADJ) {
     if (fc) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -833,7 +833,7 @@ __global__ __launch_bounds__(256, occupancy_for(T, KF)) void k_fit_batched(
     if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
     return;
   }
-  double *fc = KF && fcache ? fcache + (size_t)idx * (T * (T + 1) / 2) * 256 : nullptr;   // this row's cache slot
+  double *fc = fcache ? fcache + (size_t)idx * (T * (T + 1) / 2) * 256 : nullptr;   // this row's cache slot
   fit_row<T, KF, MT>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, dvec, status, AdjIO{}, fc);
 }
 
@@ -867,6 +867,9 @@ __global__ __launch_bounds__(256, adj_occupancy_for(T, KF)) void k_adj_regress_b
   aw.ebl = ebl[wave];
   fit_row<T, KF, MT, true>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, nullptr, status, aw);
 }
+
+// waves per SIMD of the cached-factor solves (the tiles and the vector only)
+constexpr int solve_occupancy_for(int T) { return T <= 3 ? 5 : (T == 4 ? 4 : (T == 5 ? 3 : 1)); }
 
 // ---- kernel-form adjoint from the cached factor, in three launches ---------
 // The recomputing adjoint (fit_row in ADJ mode) holds the Gram tiles in
@@ -960,7 +963,7 @@ __global__ __launch_bounds__(256) void k_adj_kf_pre(
 }
 
 template <int T>
-__global__ __launch_bounds__(256, adj_occupancy_for(T, true)) void k_adj_kf_solve(
+__global__ __launch_bounds__(256, solve_occupancy_for(T)) void k_adj_kf_solve(
     const int32_t *__restrict__ rows, int64_t nrows, int N, const double *__restrict__ fcache,
     double *__restrict__ vbuf) {
   constexpr int NT = T * (T + 1) / 2;
@@ -1050,6 +1053,167 @@ __global__ __launch_bounds__(256) void k_adj_kf_post(
   if (lane == 0) adj.lam_row[r] = ls;
 }
 
+// ---- p-form adjoint from the cached factor, in three launches ------------
+//   k_adj_pf_pre:   eps_k = u_k - sum_a beta_a U[P_a][k], e1, epsbar (into
+//                   e2) and b = betabar - U_P epsbar (into vbuf), one pass
+//                   over the members;
+//   k_adj_pf_solve: the row's tiles from the cache, x = G^-1 b by forward and
+//                   back substitution, s = (N-1) x (into sb) and the row's
+//                   share of dL/dlam;
+//   k_adj_pf_post:  e2 = -(U_P^T s/(N-1) + epsbar), one pass over the
+//                   predecessors.
+template <int T>
+__global__ __launch_bounds__(256) void k_adj_pf_pre(
+    const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
+    int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, const double *__restrict__ tval, AdjIO adj,
+    double *__restrict__ vbuf) {
+  __shared__ int spidx[4][kMaxP + 8];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+  const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
+  if (idx >= nrows) return;
+  const int64_t r = rows[idx];
+  const int64_t lo = row_ptr[r];
+  const int p = (int)(row_ptr[r + 1] - lo);
+  const int uoff = fit_glob[r] * ldu;
+  int *pidx = spidx[wave];
+  load_pidx(lane, r, blocks, fit_glob, fit_blk, col, lo, p, zrow, pidx);
+  const double nm1 = (double)(N - 1), Db = adj.dbar[r];
+  // lane (q, c) holds beta of predecessor 16I + c; one 16-byte load per tile
+  // brings members 8ks + 2q and 8ks + 2q + 1 (8 * ks2 <= ldu); the 16 lanes
+  // of a quarter sum beta_a U[P_a][k] for its two members, and vp[I] gathers
+  // sum_k U[P_{16I+c}][k] epsbar_k
+  int base[T];
+  double bet[T], vp[T];
+#pragma unroll
+  for (int I = 0; I < T; ++I) {
+    base[I] = pidx[16 * I + c] * ldu + 2 * q;
+    bet[I] = 16 * I + c < p ? -tval[lo + 16 * I + c] : 0.0;
+    vp[I] = 0.0;
+  }
+  const int ks2 = (N + 7) >> 3;
+  for (int ks = 0; ks < ks2; ++ks) {
+    double2 f[T];
+#pragma unroll
+    for (int I = 0; I < T; ++I) f[I] = *(const double2 *)&U[base[I] + 8 * ks];
+    const double2 uk = *(const double2 *)&U[uoff + 2 * q + 8 * ks];
+    double es0 = 0.0, es1 = 0.0;
+#pragma unroll
+    for (int I = 0; I < T; ++I) {
+      es0 = fma(bet[I], f[I].x, es0);
+      es1 = fma(bet[I], f[I].y, es1);
+    }
+    es0 = row16_sum(es0);
+    es1 = row16_sum(es1);
+    const int k0 = 8 * ks + 2 * q, k1 = k0 + 1;
+    const double eps0 = k0 < N ? uk.x - es0 : 0.0, eps1 = k1 < N ? uk.y - es1 : 0.0;
+    const double eb0 = 2.0 * Db * eps0 / nm1, eb1 = 2.0 * Db * eps1 / nm1;
+    if (c == 0 && k0 < N) {
+      adj.e1[r * N + k0] = eps0 / nm1;
+      adj.e2[r * N + k0] = eb0;
+    }
+    if (c == 0 && k1 < N) {
+      adj.e1[r * N + k1] = eps1 / nm1;
+      adj.e2[r * N + k1] = eb1;
+    }
+#pragma unroll
+    for (int I = 0; I < T; ++I) vp[I] = fma(f[I].y, eb1, fma(f[I].x, eb0, vp[I]));
+  }
+#pragma unroll
+  for (int I = 0; I < T; ++I) {
+    const double v = quarter_sum(vp[I]);
+    const int a = 16 * I + c;
+    if (q == 0 && a < p) vbuf[r * N + a] = adj.sb[lo + a] - v;   // b_a
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(256, solve_occupancy_for(T)) void k_adj_pf_solve(
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows, int64_t nrows, int N,
+    const double *__restrict__ tval, const double *__restrict__ fcache, const double *__restrict__ vbuf, AdjIO adj) {
+  constexpr int NT = T * (T + 1) / 2;
+  __shared__ double svec[4][16 * (T + 1)];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+  const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
+  if (idx >= nrows) return;
+  const int64_t r = rows[idx];
+  const int64_t lo = row_ptr[r];
+  const int p = (int)(row_ptr[r + 1] - lo);
+  const double *fc = fcache + (size_t)idx * NT * 256;   // the fit's slot of this row
+  d4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const double2 *src = (const double2 *)(fc + (size_t)(64 * t + lane) * 4);
+    const double2 a01 = src[0], a23 = src[1];
+    acc[t] = d4{a01.x, a01.y, a23.x, a23.y};
+  }
+  double vr[T];
+#pragma unroll
+  for (int J = 0; J < T; ++J) vr[J] = (q == 0 && 16 * J + c < p) ? vbuf[r * N + 16 * J + c] : 0.0;
+  double *y = svec[wave];
+  fwd_subst<T>(q, c, acc, vr, y, y + 16 * T);
+  back_subst<T>(q, c, acc, vr, y);
+  // s = (N-1) x overwrites betabar in sb (now b, read by the pre-pass)
+  const double nm1 = (double)(N - 1);
+  double ls = 0.0;
+  for (int a = lane; a < p; a += 64) {
+    const double sv = nm1 * y[a];
+    adj.sb[lo + a] = sv;
+    ls = fma(sv, tval[lo + a], ls);
+  }
+  ls = wave_sum(ls);
+  if (lane == 0) adj.lam_row[r] = ls;
+}
+
+template <int T, int MT>
+__global__ __launch_bounds__(256) void k_adj_pf_post(
+    const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
+    int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, AdjIO adj) {
+  __shared__ int spidx[4][kMaxP + 8];
+  __shared__ double ssl[4][kMaxP + 8];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+  const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
+  if (idx >= nrows) return;
+  const int64_t r = rows[idx];
+  const int64_t lo = row_ptr[r];
+  const int p = (int)(row_ptr[r + 1] - lo);
+  int *pidx = spidx[wave];
+  double *sl = ssl[wave];   // s, zero past p
+  for (int a = lane; a < kMaxP + 8; a += 64) sl[a] = a < p ? adj.sb[lo + a] : 0.0;
+  load_pidx(lane, r, blocks, fit_glob, fit_blk, col, lo, p, zrow, pidx);
+  // lane (q, c) sums members 16I + c over predecessors a = q mod 4, four
+  // k-steps of loads at a time (pad row past p, columns 16I + c < ldu)
+  const double nm1 = (double)(N - 1);
+  const int nt = (N + 15) >> 4;
+  const int ks4 = (((p + 3) >> 2) + 3) & ~3;
+  double e[MT];
+#pragma unroll
+  for (int I = 0; I < MT; ++I) e[I] = 0.0;
+  for (int ks0 = 0; ks0 < ks4; ks0 += 4) {
+    double f[4][MT], sv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int a = 4 * (ks0 + u) + q;
+      const int off = pidx[a] * ldu + c;
+      sv[u] = sl[a];
+#pragma unroll
+      for (int I = 0; I < MT; ++I) f[u][I] = I < nt ? U[off + 16 * I] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int I = 0; I < MT; ++I) e[I] = fma(sv[u], f[u][I], e[I]);
+  }
+#pragma unroll
+  for (int I = 0; I < MT; ++I) {
+    if (I >= nt) break;
+    const double es = quarter_sum(e[I]);
+    const int k = 16 * I + c;
+    if (q == 0 && k < N) adj.e2[r * N + k] = -(es / nm1 + adj.e2[r * N + k]);
+  }
+}
+
 // Adjoint of the regressions without predecessors (eps = u).
 __global__ __launch_bounds__(256) void k_adj_p0(const int32_t *__restrict__ fit_glob, const double *__restrict__ U,
                                                 int ldu, int N, const int32_t *__restrict__ rows, int64_t nrows,
@@ -1099,10 +1263,11 @@ static void launch_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows, int
 // N <= 80, else 8.
 template <int T>
 static void launch_pform(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam, hipStream_t s) {
+  double *fc = p->fcache ? p->fcache + fcache_offset(p, T) : nullptr;   // NULL: no factor cache
   if constexpr (T <= 5) {
-    if (p->N <= 80) return launch_bucket<T, false, 5>(p, d, rows, n, lam, s);
+    if (p->N <= 80) return launch_bucket<T, false, 5>(p, d, rows, n, lam, s, fc);
   }
-  launch_bucket<T, false, 8>(p, d, rows, n, lam, s);
+  launch_bucket<T, false, 8>(p, d, rows, n, lam, s, fc);
 }
 
 hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s) {
@@ -1128,7 +1293,7 @@ hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStrea
     // kernel form: m = N.  Without a ridge these rows (p >= N) are ENOTSPD,
     // which the p-form kernel reports before any arithmetic.
     if (lam > 0.0) {
-      double *fc = p->fcache;   // NULL: no factor cache
+      double *fc = p->fcache ? p->fcache + fcache_offset(p, kBucketKF) : nullptr;   // NULL: no factor cache
       phase_begin(p, ENKFMC_PH_FIT_KFORM, s);
       switch ((p->N + 15) / 16) {
         case 1: launch_bucket<1, true, 1>(p, d, rk, nk, lam, s, fc); break;
@@ -1178,7 +1343,8 @@ static void launch_adj_kform(enkfmc_plan *p, const Dev &d, const int32_t *rows, 
   const dim3 g((unsigned)((n + 3) / 4));
   hipLaunchKernelGGL(k_adj_kf_pre<T>, g, dim3(256), 0, s, d.blocks, d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U,
                      p->ldu, p->N, rows, n, (int)p->n, lam, d.tval, adj, d.ubar);
-  hipLaunchKernelGGL(k_adj_kf_solve<T>, g, dim3(256), 0, s, rows, n, p->N, (const double *)p->fcache, d.ubar);
+  hipLaunchKernelGGL(k_adj_kf_solve<T>, g, dim3(256), 0, s, rows, n, p->N,
+                     (const double *)p->fcache + fcache_offset(p, kBucketKF), d.ubar);
   hipLaunchKernelGGL(k_adj_kf_post<T>, g, dim3(256), 0, s, d.blocks, d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U,
                      p->ldu, p->N, rows, n, (int)p->n, lam, d.tval, adj, (const double *)d.ubar);
 }
@@ -1186,6 +1352,23 @@ static void launch_adj_kform(enkfmc_plan *p, const Dev &d, const int32_t *rows, 
 template <int T>
 static void launch_adj_pform(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam,
                              const AdjIO &adj, hipStream_t s) {
+  if (n <= 0) return;
+  if (p->fcache_valid) {
+    // the cached factor: pass over U_P^T, solve, pass over U_P (v, then s,
+    // in the Ubar buffer and in sb)
+    const dim3 g((unsigned)((n + 3) / 4));
+    hipLaunchKernelGGL(k_adj_pf_pre<T>, g, dim3(256), 0, s, d.blocks, d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U,
+                       p->ldu, p->N, rows, n, (int)p->n, (const double *)d.tval, adj, d.ubar);
+    hipLaunchKernelGGL(k_adj_pf_solve<T>, g, dim3(256), 0, s, d.row_ptr, rows, n, p->N, (const double *)d.tval,
+                       (const double *)p->fcache + fcache_offset(p, T), (const double *)d.ubar, adj);
+    if (T <= 5 && p->N <= 80)
+      hipLaunchKernelGGL((k_adj_pf_post<T, 5>), g, dim3(256), 0, s, d.blocks, d.fit_glob, d.fit_blk, d.row_ptr, d.col,
+                         d.U, p->ldu, p->N, rows, n, (int)p->n, adj);
+    else
+      hipLaunchKernelGGL((k_adj_pf_post<T, 8>), g, dim3(256), 0, s, d.blocks, d.fit_glob, d.fit_blk, d.row_ptr, d.col,
+                         d.U, p->ldu, p->N, rows, n, (int)p->n, adj);
+    return;
+  }
   if constexpr (T <= 5) {
     if (p->N <= 80) return launch_adj_bucket<T, false, 5>(p, d, rows, n, lam, adj, s);
   }

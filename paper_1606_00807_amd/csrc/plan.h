@@ -129,6 +129,21 @@ struct enkfmc_plan {
 };
 
 namespace enkfmc {
+// Factor cache (enkfmc_plan_set_factor_cache): a slot of T(T + 1)/2 tiles of
+// 256 doubles per row of the one-wavefront buckets 1..8 (p-form, T = b) and
+// of the kernel-form bucket (T = ceil(N/16)), bucket after bucket, each in
+// the bucket's row order.  fcache_tiles: T of bucket b; fcache_offset:
+// doubles before the slots of bucket b (b = kBucketKF + 1: the total).
+inline int fcache_tiles(const enkfmc_plan *p, int b) { return b == kBucketKF ? (p->N + 15) / 16 : b; }
+inline size_t fcache_offset(const enkfmc_plan *p, int b) {
+  size_t off = 0;
+  for (int k = 1; k < b && k <= kBucketKF; ++k) {
+    const size_t T = (size_t)fcache_tiles(p, k);
+    off += (size_t)(p->bucket_off[k + 1] - p->bucket_off[k]) * (T * (T + 1) / 2) * 256;
+  }
+  return off;
+}
+
 enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, const int32_t *obs_idx, int32_t m,
                          std::string *err);
 void compute_layout(enkfmc_plan *p);

@@ -113,25 +113,32 @@ def test_cycle_entry_points_validate_on_the_host():
     assert lib.enkfmc_analysis_sq_error(plan._h, fake, 1, 10, fake, fake, None) == -7
 
 
+def _cache_bytes(counts, N):
+    """T(T+1)/2 tiles of 2 KiB per regression with predecessors: T =
+    ceil(p/16) for p < N, ceil(N/16) for p >= N."""
+    T = np.where(counts < N, (counts + 15) // 16, (N + 15) // 16)
+    return int(np.sum(np.where(counts > 0, T * (T + 1) // 2, 0))) * 256 * 8
+
+
 def test_factor_cache_sizes_and_validation():
-    """enkfmc_plan_set_factor_cache: size T(T+1)/2 x 2 KiB per kernel-form row
-    (p >= N), EINVAL for a misaligned pointer, ENOMEM below the size, and NULL
-    always accepted (the fake pointers are never dereferenced)."""
+    """enkfmc_plan_set_factor_cache: size T(T+1)/2 x 2 KiB per regression of
+    the one-wavefront kernels (p-form and kernel form), EINVAL for a
+    misaligned pointer, ENOMEM below the size, and NULL always accepted (the
+    fake pointers are never dereferenced)."""
     import ctypes
     geo = synth.geometry(12, 10, [3], True, 2, 2, 1, 1)
     N = 8
     plan = Plan(geo, N, np.array([1, 5, 9], np.int32))
     counts = np.concatenate([plan.row_counts(k) for k in range(int(plan.info["n_subdomains"]))])
-    nk = int(np.sum(counts >= N))
-    assert nk > 0
-    T = (N + 15) // 16
-    need = nk * (T * (T + 1) // 2) * 256 * 8
+    assert np.sum(counts >= N) > 0 and np.sum((counts > 0) & (counts < N)) > 0
+    need = _cache_bytes(counts, N)
     assert plan.info["factor_cache_bytes"] == need
     lib = plan.lib
     assert lib.enkfmc_plan_set_factor_cache(plan._h, ctypes.c_void_p(4096 + 8), need) == -1
     assert lib.enkfmc_plan_set_factor_cache(plan._h, ctypes.c_void_p(4096), need - 1) == -6
     assert lib.enkfmc_plan_set_factor_cache(plan._h, ctypes.c_void_p(4096), need) == 0
     assert lib.enkfmc_plan_set_factor_cache(plan._h, None, 0) == 0
-    # more members than any predecessor count: no kernel-form rows, nothing to cache
+    # more members than any predecessor count: p-form rows only
     plan2 = Plan(geo, 40, np.array([1, 5, 9], np.int32))
-    assert plan2.info["factor_cache_bytes"] == 0
+    c2 = np.concatenate([plan2.row_counts(k) for k in range(int(plan2.info["n_subdomains"]))])
+    assert np.all(c2 < 40) and plan2.info["factor_cache_bytes"] == _cache_bytes(c2, 40)
