@@ -442,7 +442,7 @@ def main():
     ap.add_argument("--no-small", action="store_true",
                     help="skip the ring40 and grid96x48 lines (batched vs plain, error vs the whole oracle)")
     ap.add_argument("--no-factor-cache", action="store_true",
-                    help="skip the reverse pass with the fit's kernel-form factors cached")
+                    help="skip the reverse pass with the fit's factors cached")
     ap.add_argument("--adjoint-steps", type=int, default=3,
                     help="also time fit + analyze + enkfmc_analyze_backward this many times (0: skip)")
     ap.add_argument("--cycles", type=int, default=4,
@@ -557,7 +557,7 @@ def main():
         log(f"adjoint: {adjoint['ms_backward']:.2f} ms; phases(ms) "
             + ", ".join(f"{k}={v:.3f}" for k, v in adjoint["phases_ms"].items()))
         if not args.no_factor_cache:
-            # the same with the kernel-form factors kept by each fit: forward
+            # the same with the regressions' factors kept by each fit: forward
             # step and reverse pass timed uninstrumented, then one pass for phases
             nbytes = plan.set_factor_cache(True)
             step(args.mode)
@@ -582,7 +582,7 @@ def main():
             adjoint["factor_cache"] = {
                 "bytes": nbytes, "ms_forward_step": tf / args.adjoint_steps * 1e3,
                 "ms_backward": tr / args.adjoint_steps * 1e3, "phases_ms": ph,
-                "note": "enkfmc_plan_set_factor_cache: each fit keeps the kernel-form Cholesky tiles, "
+                "note": "enkfmc_plan_set_factor_cache: each fit keeps the regressions' Cholesky tiles, "
                         "the reverse pass reads them"}
             log(f"adjoint with factor cache ({nbytes / 2**30:.1f} GiB): forward step "
                 f"{adjoint['factor_cache']['ms_forward_step']:.2f} ms, reverse pass "
