@@ -296,7 +296,7 @@ def small_config(name, mode_steps=10):
     return out
 
 
-def c5_bench(replays: int, branches: int) -> dict:
+def c5_bench(replays: int, branches) -> dict:
     """The uneven batch: 64 independent instances (grids 32x16 to 192x96, 1-7
     levels, N 20-120, r 1-5, 2-30% observed), fit + analysis of all of them in
     one captured HIP graph; aggregate components/s over the graph replay and
@@ -312,7 +312,7 @@ def c5_bench(replays: int, branches: int) -> dict:
     from oracle import fit as OF
     from oracle import geometry as OG
     from paper_1606_00807_amd import Plan
-    from paper_1606_00807_amd.graph import InstanceGraph
+    from paper_1606_00807_amd.graph import InstanceGraph, tune_branches
 
     params = synth.instance_params()
     probs = [synth.make_instance(k, params) for k in range(len(params))]
@@ -324,9 +324,19 @@ def c5_bench(replays: int, branches: int) -> dict:
             plan = Plan(p.geometry, p.N, p.obs_idx)
             items.append(dict(plan=plan, Xb=torch.as_tensor(p.Xb).cuda(), Y=torch.as_tensor(p.Y).cuda(),
                               r_diag=torch.as_tensor(p.r_diag).cuda(), ridge=p.ridge, mode=mode))
+        nb = branches
+        if nb is None:
+            # branch count tuned on the eager runs of this instance set (cache:
+            # ENKFMC_TUNE_CACHE, else under the user's cache directory)
+            cache = os.environ.get("ENKFMC_TUNE_CACHE",
+                                   os.path.join(os.path.expanduser("~"), ".cache", "enkfmc", "tune.json"))
+            nb, table = tune_branches(items, cache=cache)
+            out[f"branches_{mode}"] = nb
+            out[f"branch_tuning_ms_{mode}"] = table
+            log(f"c5 {mode}: branch counts (eager ms) {table} -> {nb}")
         # batched: the captured graph; plain: the same enqueue order run
         # without a graph (asynchronous plans on the same branch streams)
-        g = InstanceGraph(items, branches=branches)
+        g = InstanceGraph(items, branches=nb)
         g.run_eager()
         if mode == "batched":
             g.capture()
@@ -440,7 +450,8 @@ def main():
                     help="also time this many fit steps in the SVD mode (Section 5 route; 0: skip)")
     ap.add_argument("--c5", action="store_true",
                     help="also run the uneven batch of 64 instances in one HIP graph (p50/p99 latency)")
-    ap.add_argument("--c5-branches", type=int, default=4)
+    ap.add_argument("--c5-branches", type=int, default=None,
+                    help="branch count of the instance graph (default: tuned per instance set and cached)")
     ap.add_argument("--c5-replays", type=int, default=10)
     ap.add_argument("--pcg-steps", type=int, default=1,
                     help="also time this many analyses with the PCG solver (0: skip)")

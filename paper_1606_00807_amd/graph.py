@@ -15,7 +15,10 @@ library's.
 """
 from __future__ import annotations
 
-from typing import Dict, List, Sequence
+import hashlib
+import json
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -103,3 +106,63 @@ class InstanceGraph:
         for it in self.items:
             it["plan"].set_async(False)
         self.graph = None
+
+
+def _tune_key(items: Sequence[Dict]) -> str:
+    """Device architecture and a digest of the instance set (each plan's n,
+    N, largest predecessor count, regressions, observations and fit mode)."""
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    sig = sorted((int(it["plan"].info["n"]), int(it["plan"].N), int(it["plan"].info["max_p"]),
+                  int(it["plan"].info["n_fit"]), int(it["plan"].info["m"]), str(it.get("mode", "batched")))
+                 for it in items)
+    return arch + ":" + hashlib.sha1(repr(sig).encode()).hexdigest()[:16]
+
+
+def tune_branches(items: Sequence[Dict], candidates: Sequence[int] = (1, 2, 4, 8, 16), reps: int = 3,
+                  cache: Optional[str] = None) -> Tuple[int, Dict[int, float]]:
+    """Branch count of an InstanceGraph for these instances: each candidate's
+    eager run (the same enqueue order on the branch streams, no graph) timed
+    by events, median of reps after one warm-up; the fastest wins.  With a
+    cache file (JSON), a result for the same device architecture and
+    instance set is reused and new results are stored; an unreadable or
+    unwritable cache is ignored.  Returns (branches, ms per candidate)."""
+    import torch
+    key = _tune_key(items)
+    table: Dict = {}
+    if cache:
+        try:
+            with open(cache) as f:
+                table = json.load(f)
+        except (OSError, ValueError):
+            table = {}
+        hit = table.get(key)
+        if isinstance(hit, dict) and "branches" in hit:
+            return int(hit["branches"]), {int(k): float(v) for k, v in hit.get("ms", {}).items()}
+    times: Dict[int, float] = {}
+    for b in candidates:
+        if b > len(items):
+            continue
+        g = InstanceGraph(items, branches=b)
+        g.run_eager()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(reps):
+            ev0.record()
+            g._enqueue()
+            ev1.record()
+            torch.cuda.synchronize()
+            ms.append(ev0.elapsed_time(ev1))
+        g.check()
+        g.close()
+        times[b] = float(np.median(ms))
+    best = min(times, key=times.get)
+    if cache:
+        table[key] = {"branches": best, "ms": {str(k): v for k, v in times.items()}}
+        try:
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        except OSError:
+            pass
+    return best, times

@@ -96,3 +96,30 @@ def test_c5_graph_instance_matches_oracle(c5, k):
     em = float(np.linalg.norm(Xa[rows].mean(1) - ref.mean(1)) / np.linalg.norm(ref.mean(1)))
     _say(f"[c5 graph {k}] N={p.N} sub-domain {ks}: T={et:.2e} D={ed:.2e} Z={ez:.2e} X_a mean={em:.2e}")
     assert et <= 1e-9 and ed <= 1e-9 and ez <= 1e-8 and em <= 1e-6
+
+
+def test_branch_tuning_picks_a_candidate_and_caches_it(tmp_path):
+    """tune_branches times the eager runs of a small instance set for each
+    branch count, returns the fastest, and a second call with the same cache
+    file returns the stored choice; the instances' results do not depend on
+    the branch count."""
+    from paper_1606_00807_amd.graph import tune_branches
+    items = []
+    for k in range(6):
+        p = synth.make_instance(k, PARAMS)
+        items.append(dict(plan=Plan(p.geometry, p.N, p.obs_idx), Xb=torch.as_tensor(p.Xb).cuda(),
+                          Y=torch.as_tensor(p.Y).cuda(), r_diag=torch.as_tensor(p.r_diag).cuda(), ridge=p.ridge))
+    cache = str(tmp_path / "tune.json")
+    best, table = tune_branches(items, candidates=(1, 2, 4), reps=2, cache=cache)
+    _say(f"[c5 tune] {table} -> {best}")
+    assert best in (1, 2, 4) and set(table) == {1, 2, 4} and table[best] == min(table.values())
+    again, table2 = tune_branches(items, candidates=(1, 2, 4), reps=2, cache=cache)
+    assert again == best and table2 == table
+    outs = []
+    for b in (1, best):
+        g = InstanceGraph(items, branches=b)
+        outs.append(g.run_eager())
+        g.close()
+    assert all(torch.equal(a, b) for a, b in zip(*outs))
+    for it in items:
+        it["plan"].close()
