@@ -57,7 +57,10 @@ def phase_roofline(info, N, phases, xb_bytes, fit_all_flops, fit_kf_flops):
         "anomaly": ("hbm", n * N * xb_bytes + n * (-(-N // 16) * 16) * 8 + n * 8),
         "fit": ("fp64", fit_all_flops),
         "fit_kform": ("fp64", fit_kf_flops),
-        "tiles": ("hbm", info["nnz"] * 12 + (info["n_tiles"] + 2 * info["n_row_tiles"]) * 2048),
+        # the batched fit writes the tiles itself unless some rows take the
+        # plain kernel; the phase is then the diagonal tiles' inverses only
+        "tiles": ("hbm", 2 * info["n_row_tiles"] * 2048 if info.get("fit_rows_plain", 1) == 0
+                  else info["nnz"] * 12 + (info["n_tiles"] + 2 * info["n_row_tiles"]) * 2048),
         "dual_F": ("hbm", tiles_b + info["f_entries"] * 8),
         "dual_S": ("hbm", info["f_entries"] * 8 + info["s_entries"] * 8 + nf * 8),
         "dual_chol": ("hbm", info["s_entries"] * 8 * 2),

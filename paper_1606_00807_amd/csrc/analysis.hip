@@ -699,6 +699,45 @@ int max_block_tiles(const enkfmc_plan *p) {
   return mx;
 }
 
+// Inverse of every diagonal tile, (I + L)^-1 with L its strictly lower part
+// (tdiag), when the fit has written the tiles itself: 16 row tiles per
+// workgroup, staged in LDS, 16 lanes each (column j by forward substitution,
+// the same arithmetic as k_build_tiles).
+__global__ __launch_bounds__(256) void k_tile_inverse(const double *__restrict__ tdiag, int64_t n_rt,
+                                                      double *__restrict__ tinv) {
+  __shared__ double sd[16 * 256];
+  const int grp = threadIdx.x >> 4, j = threadIdx.x & 15;
+  const int64_t base = (int64_t)blockIdx.x * 16;
+  for (int e = threadIdx.x; e < 16 * 256; e += 256) {
+    const int64_t t = base + (e >> 8);
+    sd[e] = t < n_rt ? tdiag[t * 256 + (e & 255)] : 0.0;
+  }
+  __syncthreads();
+  const int64_t rt = base + grp;
+  if (rt >= n_rt) return;
+  const double *diag = sd + grp * 256;
+  double x[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= diag[i * 16 + k] * x[k];
+    x[i] = (i < j) ? 0.0 : v;
+  }
+  double *dst = tinv + rt * 256;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) dst[i * 16 + j] = x[i];
+}
+
+hipError_t launch_tile_inverse(enkfmc_plan *p, const Dev &d, hipStream_t s) {
+  phase_begin(p, ENKFMC_PH_TILES, s);
+  if (p->n_rt > 0)
+    hipLaunchKernelGGL(k_tile_inverse, dim3((unsigned)((p->n_rt + 15) / 16)), dim3(256), 0, s, d.tdiag,
+                       (int64_t)p->n_rt, d.tinv);
+  phase_end(p, ENKFMC_PH_TILES, s);
+  return hipGetLastError();
+}
+
 hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s) {
   phase_begin(p, ENKFMC_PH_TILES, s);
   hipLaunchKernelGGL(k_build_tiles, dim3((unsigned)p->blocks.size(), (unsigned)max_block_tiles(p)), dim3(64), 0, s,

@@ -203,6 +203,10 @@ enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes,
   HIPCHK(put(p, L.ct_row, p->ct_row, s), "set_workspace");
   HIPCHK(put(p, L.ct_slot, p->ct_slot, s), "set_workspace");
   HIPCHK(put(p, L.tile_eoff, p->tile_eoff, s), "set_workspace");
+  // the dense tiles of T hold zeros off the pattern, which no kernel writes
+  // (the batched fit writes pattern positions only)
+  HIPCHK(hipMemsetAsync(p->ws + L.tiles, 0, (size_t)p->n_slots * 256 * sizeof(double), s), "set_workspace");
+  HIPCHK(hipMemsetAsync(p->ws + L.tdiag, 0, (size_t)p->n_rt * 256 * sizeof(double), s), "set_workspace");
   HIPCHK(clear_status(p, s), "set_workspace");
   HIPCHK(hipStreamSynchronize(s), "set_workspace");
   return ENKFMC_OK;
@@ -236,7 +240,11 @@ enkfmc_status enkfmc_fit(enkfmc_plan *p, const void *Xb, int32_t dtype, int64_t 
   } else {
     HIPCHK(launch_fit_batched(p, d, ridge, s), "fit: batched launch");
   }
-  HIPCHK(launch_build_tiles(p, d, s), "fit: tile launch");
+  if (mode == ENKFMC_FIT_BATCHED && fit_writes_tiles(p)) {
+    HIPCHK(launch_tile_inverse(p, d, s), "fit: tile inverse launch");
+  } else {
+    HIPCHK(launch_build_tiles(p, d, s), "fit: tile launch");
+  }
   st = finish(p, s, "fit");
   if (st != ENKFMC_OK) return st;
   p->fitted = 1;

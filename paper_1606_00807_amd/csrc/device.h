@@ -217,6 +217,8 @@ hipError_t launch_fit_batched(enkfmc_plan *p, const Dev &d, double lam, hipStrea
 hipError_t launch_fit_svd(enkfmc_plan *p, const Dev &d, double lam, hipStream_t s);
 size_t fit_svd_max_lds(const enkfmc_plan *p, double lam);   // LDS of the largest SVD regression
 hipError_t launch_build_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s);
+bool fit_writes_tiles(const enkfmc_plan *p);   // the batched fit writes the dense tiles of T itself
+hipError_t launch_tile_inverse(enkfmc_plan *p, const Dev &d, hipStream_t s);   // tinv from tdiag
 int max_block_tiles(const enkfmc_plan *p);
 hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const double *V, double *out,
                             hipStream_t s);

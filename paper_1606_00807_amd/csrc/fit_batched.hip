@@ -54,10 +54,49 @@ namespace enkfmc {
 
 constexpr int kMaxT = 8;          // largest tile count handled here (m <= 128, N <= 128)
 constexpr int kMaxP = 192;        // largest predecessor count handled here
+constexpr int kTileMapFit = 128;  // row-tile distances R - C mapped in LDS (beyond: bisection)
+
+// Dense tiles of T written by the fit itself (when the whole plan runs the
+// one-wavefront kernels): a coefficient of row r goes to T_RC (row-major,
+// 16 x 16) at (r mod 16, c mod 16), or to the strictly lower diagonal tile.
+// The tiles hold zeros off the pattern from the workspace's adoption on, and
+// only pattern positions are ever written.
+struct TileOut {
+  double *tiles, *tdiag;          // NULL tiles: not written here
+  const int64_t *rt_ptr;
+  const int32_t *rt_col, *rt_slot, *col;
+};
+// Destination of a coefficient of a row in row tile R of its block, row i of
+// the tile, global row tile rt whose tile list starts at t0 (nt tiles), at
+// local column colidx: an index into the tiles (>= 0), or -1 - index into
+// the diagonal tiles.  tmap holds the slots of the list at R - C.
+__device__ __forceinline__ int tile_dest(const TileOut &to, int R, int i, int64_t rt, int64_t t0, int nt,
+                                         const int *tmap, int colidx) {
+  const int C = colidx >> 4, j = colidx & 15;
+  if (C == R) return -1 - (int)(rt * 256 + i * 16 + j);
+  int slot;
+  if (R - C < kTileMapFit) {
+    slot = tmap[R - C];
+  } else {   // list position by bisection (column tiles ascending)
+    int lo = 0, hi = nt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (to.rt_col[t0 + mid] < C) lo = mid + 1; else hi = mid;
+    }
+    slot = to.rt_slot[t0 + lo];
+  }
+  return slot * 256 + i * 16 + j;
+}
+__device__ __forceinline__ void put_tile(double *tiles, double *tdiag, int d, double v) {
+  if (d >= 0) tiles[d] = v;
+  else tdiag[-1 - d] = v;
+}
 
 template <int T>
 struct WaveLds {                  // wavefront-private LDS (doubles unless noted)
   int pidx[kMaxP + 8];            // global rows of the predecessors, pad row beyond p
+  int tmap[kTileMapFit];          // tile slot of column tile C of the row's row tile, at R - C
+  int tdst[kMaxP];                // where coefficient a goes: tiles[d] (d >= 0) or tdiag[-1 - d]
   double vec[16 * (T + 1)];
   double tile[kMaxP + 16 * kMaxT]; // scratch: bordering row, adjoint vectors
 };
@@ -323,7 +362,8 @@ template <int T, bool KF, int MT, bool ADJ = false>
 __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const int p, const int N, const double mu,
                                         const double *__restrict__ U, const int ldu, const int uoff, WaveLds<T> &L,
                                         double *__restrict__ tval, const int64_t lo, double *__restrict__ dvec,
-                                        int32_t *status, const AdjIO &adj, double *__restrict__ fc = nullptr) {
+                                        int32_t *status, const AdjIO &adj, double *__restrict__ fc = nullptr,
+                                        double *__restrict__ ttiles = nullptr, double *__restrict__ tdiag = nullptr) {
   constexpr int NT = T * (T + 1) / 2;
   const int q = lane >> 4, c = lane & 15;
   const int m = KF ? N : p;
@@ -667,7 +707,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
       // lanes 4u..4u+3 get beta of predecessor 4(ks0 + u) + q
       const double b = row16_sum4(bu[0], bu[1], bu[2], bu[3], c);
       const int a = 4 * (ks0 + (c >> 2)) + q;
-      if ((c & 3) == 0 && a < p) tval[lo + a] = -b;
+      if ((c & 3) == 0 && a < p) {
+        tval[lo + a] = -b;
+        if (ttiles) put_tile(ttiles, tdiag, L.tdst[a], -b);
+      }
     }
     if (q == 0) {
 #pragma unroll
@@ -679,7 +722,10 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   } else {
     // eps_k = u_k - sum_a beta_a U[P_a][k]: lane (q, c) takes member 16I + c and
     // predecessors a = q mod 4; the four partial sums are then added across q.
-    for (int a = lane; a < p; a += 64) tval[lo + a] = -y[a];
+    for (int a = lane; a < p; a += 64) {
+      tval[lo + a] = -y[a];
+      if (ttiles) put_tile(ttiles, tdiag, L.tdst[a], -y[a]);
+    }
     // one pointer per predecessor; the member tiles then differ by constant
     // offsets (the loop over them is unrolled, N <= 16 MT)
     double bq[4 * T];
@@ -816,7 +862,7 @@ __global__ __launch_bounds__(256, occupancy_for(T, KF)) void k_fit_batched(
     const Block *__restrict__ blocks, const int32_t *__restrict__ fit_glob, const int32_t *__restrict__ fit_blk,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ U, int ldu,
     int N, const int32_t *__restrict__ rows, int64_t nrows, int zrow, double lam, double *__restrict__ tval,
-    double *__restrict__ dvec, int32_t *status, double *__restrict__ fcache) {
+    double *__restrict__ dvec, int32_t *status, double *__restrict__ fcache, TileOut to) {
   __shared__ WaveLds<T> lds[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
@@ -827,14 +873,39 @@ __global__ __launch_bounds__(256, occupancy_for(T, KF)) void k_fit_batched(
   const int64_t lo = row_ptr[r];
   const int p = (int)(row_ptr[r + 1] - lo);
   const int uoff = fit_glob[r] * ldu;
-  for (int k = lane; k < kMaxP + 8; k += 64) L.pidx[k] = k < p ? fit_glob[B.row0 + col[lo + k]] : zrow;
+  if (!to.tiles) {
+    for (int k = lane; k < kMaxP + 8; k += 64) L.pidx[k] = k < p ? fit_glob[B.row0 + col[lo + k]] : zrow;
+  } else {
+    // the predecessors' rows and each coefficient's place in the dense tiles,
+    // from one read of the columns (the row tile's slots mapped first)
+    const int local = (int)(r - B.row0);
+    const int R = local >> 4, i = local & 15;
+    const int64_t rt = B.rt0 + R;
+    const int64_t t0 = to.rt_ptr[rt];
+    const int nt = (int)(to.rt_ptr[rt + 1] - t0);
+    for (int t = lane; t < nt; t += 64) {
+      const int d = R - to.rt_col[t0 + t];
+      if (d < kTileMapFit) L.tmap[d] = to.rt_slot[t0 + t];
+    }
+    wave_lds_sync();
+    for (int k = lane; k < kMaxP + 8; k += 64) {
+      if (k < p) {
+        const int cc = col[lo + k];
+        L.pidx[k] = fit_glob[B.row0 + cc];
+        L.tdst[k] = tile_dest(to, R, i, rt, t0, nt, L.tmap, cc);
+      } else {
+        L.pidx[k] = zrow;
+      }
+    }
+  }
   wave_lds_sync();
   if (!KF && lam == 0.0 && p >= N - 1) {
     if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
     return;
   }
   double *fc = fcache ? fcache + (size_t)idx * (T * (T + 1) / 2) * 256 : nullptr;   // this row's cache slot
-  fit_row<T, KF, MT>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, dvec, status, AdjIO{}, fc);
+  fit_row<T, KF, MT>(lane, r, p, N, lam * (double)(N - 1), U, ldu, uoff, L, tval, lo, dvec, status, AdjIO{}, fc,
+                     to.tiles, to.tdiag);
 }
 
 // Adjoint of the regressions of one bucket (same rows and shapes as the fit).
@@ -1250,13 +1321,25 @@ __global__ __launch_bounds__(256) void k_fit_p0(const int32_t *__restrict__ fit_
   }
 }
 
+// The tiles of T are written by the fit when every row runs a one-wavefront
+// kernel (no plain bucket); otherwise k_build_tiles assembles them after it.
+// (destinations are 32-bit indices: at most 2^31 / 256 tiles)
+bool fit_writes_tiles(const enkfmc_plan *p) {
+  return p->bucket_off[kBucketPlain + 1] == p->bucket_off[kBucketPlain] && (int64_t)p->n_slots < (1ll << 23) &&
+         (int64_t)p->n_rt < (1ll << 23);
+}
+
+static TileOut tile_out(const enkfmc_plan *p, const Dev &d) {
+  return TileOut{fit_writes_tiles(p) ? d.tiles : nullptr, d.tdiag, d.rt_ptr, d.rt_col, d.rt_slot, d.col};
+}
+
 template <int T, bool KF, int MT>
 static void launch_bucket(enkfmc_plan *p, const Dev &d, const int32_t *rows, int64_t n, double lam, hipStream_t s,
                           double *fcache = nullptr) {
   if (n <= 0) return;
   hipLaunchKernelGGL((k_fit_batched<T, KF, MT>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d.blocks,
                      d.fit_glob, d.fit_blk, d.row_ptr, d.col, d.U, p->ldu, p->N, rows, n, (int)p->n, lam, d.tval,
-                     d.dvec, d.status, fcache);
+                     d.dvec, d.status, fcache, tile_out(p, d));
 }
 
 // p-form bucket of T tiles: the residual loops unroll 5 member tiles when
