@@ -681,6 +681,123 @@ __global__ __launch_bounds__(64) void k_fwd_sweep_ring(const Block *__restrict__
   }
 }
 
+// The forward sweep split by tile distance.  With D the plan's near distance
+// (every distance 1..D occurs, the stored tiles further back are "far"),
+// the row tiles go in chunks of D + 1: a far tile T_RC of a chunk's row tile
+// has C in an earlier chunk, so the far sums G_R - sum_far T_RC Z_C of the
+// whole chunk are independent products, read from memory, accumulated in
+// registers at the chunk's start; the near tiles follow row tile by row tile
+// from a ring of the last D Z tiles in LDS (D x 2 KB, not the largest
+// distance x 2 KB of k_fwd_sweep_ring), so several chains share a SIMD.  The
+// far T rows are loaded four consecutive doubles per lane (k-step kc takes
+// column 4q + kc).  One wavefront per (block, member tile).
+template <int D>
+__global__ __launch_bounds__(64) void k_fwd_sweep_near(const Block *__restrict__ blocks, int ng,
+                                                       const int64_t *__restrict__ rt_ptr,
+                                                       const int32_t *__restrict__ rt_col,
+                                                       const int32_t *__restrict__ rt_slot,
+                                                       const int32_t *__restrict__ rt_nfar,
+                                                       const double *__restrict__ tiles,
+                                                       const double *__restrict__ tinv, int N,
+                                                       double *__restrict__ Z) {
+  constexpr int W = D + 1;
+  constexpr int kFarBatch = 4;   // far tiles whose loads are issued together
+  __shared__ double ring[D * 256];
+  const int64_t lg = xcd_contiguous(blockIdx.x, gridDim.x);
+  const Block B = blocks[lg / ng];
+  const int cc = (int)(lg % ng);
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int colj = 16 * cc + c;
+  const bool colok = colj < N;
+  double *Zb = Z + B.row0 * N;
+  const int64_t *rp = rt_ptr + B.rt0;
+  for (int k0 = 0; k0 < B.nrt; k0 += W) {
+    d4 acc[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int R = k0 + j;
+      acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+      if (R >= B.nrt) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * R + 4 * r + q;
+        acc[j][r] = (row < B.n && colok) ? Zb[(int64_t)row * N + colj] : 0.0;   // G_R
+      }
+      // far tiles (the first rt_nfar of the ascending list, C < R - D): Z_C
+      // from memory, kFarBatch tiles' loads issued before their products
+      const int64_t tf0 = rp[R], tf1 = tf0 + rt_nfar[B.rt0 + R];
+      for (int64_t tb = tf0; tb < tf1; tb += kFarBatch) {
+        double ta[kFarBatch][4], zv[kFarBatch][4];
+#pragma unroll
+        for (int u = 0; u < kFarBatch; ++u) {
+          const bool in = tb + u < tf1;
+          const int64_t t = in ? tb + u : tf0;
+          const int C = rt_col[t];
+          const d2 *Tt = (const d2 *)(tiles + (int64_t)rt_slot[t] * 256 + c * 16 + 4 * q);   // A: T_RC(c, 4q + kc)
+          const d2 lo = Tt[0], hi = Tt[1];
+          ta[u][0] = in ? lo[0] : 0.0; ta[u][1] = in ? lo[1] : 0.0;
+          ta[u][2] = in ? hi[0] : 0.0; ta[u][3] = in ? hi[1] : 0.0;
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) {
+            const int row = 16 * C + 4 * q + kc;   // B: Z_C(4q + kc, c)
+            zv[u][kc] = (row < B.n && colok) ? Zb[(int64_t)row * N + colj] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kFarBatch; ++u)
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) acc[j] = mfma64(-ta[u][kc], zv[u][kc], acc[j]);
+      }
+    }
+    // near tiles, row tile by row tile
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int R = k0 + j;
+      if (R >= B.nrt) break;
+      d4 a0 = acc[j], a1 = d4{0.0, 0.0, 0.0, 0.0};
+      // near tiles (at most D, distances 1..D): their loads issued together
+      const int64_t tn0 = rp[R] + rt_nfar[B.rt0 + R], tn1 = rp[R + 1];
+      d2 nlo[D], nhi[D];
+      int ncol[D];
+#pragma unroll
+      for (int u = 0; u < D; ++u) {
+        ncol[u] = -1;
+        nlo[u] = nhi[u] = d2{0.0, 0.0};
+        if (tn0 + u < tn1) {   // uniform over the wavefront
+          ncol[u] = rt_col[tn0 + u];
+          const d2 *Tt = (const d2 *)(tiles + (int64_t)rt_slot[tn0 + u] * 256 + c * 16 + 4 * q);
+          nlo[u] = Tt[0];
+          nhi[u] = Tt[1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < D; ++u) {
+        if (ncol[u] < 0) break;
+        const double *zr = ring + (ncol[u] % D) * 256 + 64 * q + c;   // B operand: Z_C(4q + kc, c)
+        a0 = mfma64(-nlo[u][0], zr[0], a0);
+        a1 = mfma64(-nhi[u][0], zr[32], a1);
+        a0 = mfma64(-nlo[u][1], zr[16], a0);
+        a1 = mfma64(-nhi[u][1], zr[48], a1);
+      }
+      const d4 sum = a0 + a1;
+      // Z_R = T_RR^-1 (G_R - sum_C T_RC Z_C)
+      const double *Ti = tinv + (B.rt0 + R) * 256 + c * 16 + q;
+      d4 out = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) out = mfma64(Ti[4 * kc], sum[kc], out);
+      wave_lds_sync();   // every read of the slot's previous tile (Z_{R-D}) is done
+      double *slot = ring + (R % D) * 256 + 16 * q + c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        slot[64 * r] = out[r];
+        const int row = 16 * R + 4 * r + q;
+        if (colok && row < B.n) Zb[(int64_t)row * N + colj] = out[r];
+      }
+      wave_lds_sync();
+    }
+  }
+}
+
 // X_a = X_b + Z on interior rows (each component has exactly one source row).
 template <typename TX, typename TO>
 __global__ __launch_bounds__(256) void k_mapback(const TX *__restrict__ Xb, int64_t ld,
@@ -756,12 +873,27 @@ hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const
   phase_begin(p, ENKFMC_PH_SWEEP, s);
   const int ng = (p->N + 15) / 16;
   const int W = std::max(1, (int)p->max_rt_back);
-  if ((size_t)W * 2048 <= kRingMaxBytes)
+#define FWD_NEAR(DD)                                                                                           \
+  hipLaunchKernelGGL(k_fwd_sweep_near<DD>, dim3(nb * (unsigned)ng), dim3(64), 0, s, d.blocks, ng, d.rt_ptr,     \
+                     d.rt_col, d.rt_slot, d.rt_nfar, d.tiles, d.tinv, p->N, out)
+  if (p->near_d < W) {   // far tiles exist: the split sweep
+    switch (p->near_d) {
+      case 1: FWD_NEAR(1); break;
+      case 2: FWD_NEAR(2); break;
+      case 3: FWD_NEAR(3); break;
+      case 4: FWD_NEAR(4); break;
+      case 5: FWD_NEAR(5); break;
+      case 6: FWD_NEAR(6); break;
+      case 7: FWD_NEAR(7); break;
+      default: FWD_NEAR(8); break;
+    }
+  } else if ((size_t)W * 2048 <= kRingMaxBytes)
     hipLaunchKernelGGL(k_fwd_sweep_ring, dim3(nb * (unsigned)ng), dim3(64), (size_t)W * 2048, s, d.blocks, ng,
                        d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tinv, p->N, W, out);
   else
     hipLaunchKernelGGL(k_fwd_sweep, dim3(nb, (unsigned)ng), dim3(64), 0, s, d.blocks, d.rt_ptr, d.rt_col, d.rt_slot,
                        d.tiles, d.tinv, p->N, out);
+#undef FWD_NEAR
   phase_end(p, ENKFMC_PH_SWEEP, s);
   return hipGetLastError();
 }

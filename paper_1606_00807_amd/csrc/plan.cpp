@@ -253,6 +253,25 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
       ++p->n_rt;
     }
   }
+  {
+    // distances R - C of the stored tiles; the split sweeps take the first
+    // contiguous run 1..d of them as near (at most 8)
+    std::vector<char> seen((size_t)p->max_rt_back + 2, 0);
+    for (const Block &B : p->blocks)
+      for (int32_t R = 0; R < B.nrt; ++R)
+        for (int64_t t = p->rt_ptr[B.rt0 + R]; t < p->rt_ptr[B.rt0 + R + 1]; ++t) seen[(size_t)(R - p->rt_col[t])] = 1;
+    int32_t d = 0;
+    while (d + 1 < (int32_t)seen.size() && seen[(size_t)d + 1] && d < 8) ++d;
+    p->near_d = std::max(d, 1);
+    p->rt_nfar.assign((size_t)p->n_rt, 0);
+    for (const Block &B : p->blocks)
+      for (int32_t R = 0; R < B.nrt; ++R) {
+        int32_t nf = 0;
+        for (int64_t t = p->rt_ptr[B.rt0 + R]; t < p->rt_ptr[B.rt0 + R + 1]; ++t)
+          if (R - p->rt_col[t] > p->near_d) ++nf;
+        p->rt_nfar[(size_t)(B.rt0 + R)] = nf;
+      }
+  }
   if (p->n_slots >= (int64_t(1) << 31)) { *err = "too many tiles"; return ENKFMC_EUNSUPPORTED; }
   if (p->max_p > 65535) { *err = "too many predecessors"; return ENKFMC_EUNSUPPORTED; }
   p->tile_eoff.assign((size_t)16 * (p->n_slots + p->n_rt), 0);
@@ -330,6 +349,7 @@ void compute_layout(enkfmc_plan *p) {
   L.rt_ptr = take((size_t)(p->n_rt + 1) * 8);
   L.rt_col = take(p->rt_col.size() * 4);
   L.rt_slot = take(p->rt_slot.size() * 4);
+  L.rt_nfar = take(p->rt_nfar.size() * 4 + 4);
   L.ct_ptr = take((size_t)(p->n_rt + 1) * 8);
   L.ct_row = take(p->ct_row.size() * 4);
   L.ct_slot = take(p->ct_slot.size() * 4);
