@@ -200,6 +200,7 @@ enkfmc_status enkfmc_plan_set_workspace(enkfmc_plan *p, void *dev, size_t bytes,
   HIPCHK(put(p, L.rt_col, p->rt_col, s), "set_workspace");
   HIPCHK(put(p, L.rt_slot, p->rt_slot, s), "set_workspace");
   HIPCHK(put(p, L.rt_nfar, p->rt_nfar, s), "set_workspace");
+  HIPCHK(put(p, L.ct_nfar, p->ct_nfar, s), "set_workspace");
   HIPCHK(put(p, L.ct_ptr, p->ct_ptr, s), "set_workspace");
   HIPCHK(put(p, L.ct_row, p->ct_row, s), "set_workspace");
   HIPCHK(put(p, L.ct_slot, p->ct_slot, s), "set_workspace");

@@ -87,6 +87,104 @@ __global__ __launch_bounds__(64) void k_adj_bwd_sweep(const Block *__restrict__ 
   }
 }
 
+// V = T^-T Zbar split by tile distance (as the forward sweep): column tiles
+// descend in chunks of D + 1; a far tile T_RC (R - C > D, a suffix of the
+// column's ascending list) has R in a later chunk, so the chunk's far sums are
+// independent products with V_R from memory, four tiles' loads at a time; the
+// near tiles follow from a ring of the last D V tiles in LDS.  One wavefront
+// per (block, 16 member columns), XCD-contiguous.
+template <int D>
+__global__ __launch_bounds__(64) void k_adj_bwd_sweep_near(const Block *__restrict__ blocks, int ng,
+                                                           const int64_t *__restrict__ ct_ptr,
+                                                           const int32_t *__restrict__ ct_row,
+                                                           const int32_t *__restrict__ ct_slot,
+                                                           const int32_t *__restrict__ ct_nfar,
+                                                           const int32_t *__restrict__ fit_glob,
+                                                           const int32_t *__restrict__ interior_src,
+                                                           const double *__restrict__ tiles,
+                                                           const double *__restrict__ tinv,
+                                                           const double *__restrict__ dXa, int N,
+                                                           double *__restrict__ V) {
+  constexpr int W = D + 1;
+  constexpr int kFarBatch = 4;
+  __shared__ double ring[D * 256];
+  const int64_t lg = xcd_contiguous(blockIdx.x, gridDim.x);
+  const Block B = blocks[lg / ng];
+  const int cc = (int)(lg % ng);
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int colj = 16 * cc + c;
+  const bool colok = colj < N;
+  double *Vb = V + B.row0 * N;
+  const int64_t *cp = ct_ptr + B.rt0;
+  for (int C0 = B.nrt - 1; C0 >= 0; C0 -= W) {
+    d4 acc[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int C = C0 - j;
+      acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+      if (C < 0) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * C + 4 * r + q;
+        acc[j][r] = (row < B.n && colok) ? zbar_of(fit_glob, interior_src, dXa, N, B.row0 + row, colj) : 0.0;
+      }
+      const int64_t tf1 = cp[C + 1], tf0 = tf1 - ct_nfar[B.rt0 + C];
+      for (int64_t tb = tf0; tb < tf1; tb += kFarBatch) {
+        double ta[kFarBatch][4], vv[kFarBatch][4];
+#pragma unroll
+        for (int u = 0; u < kFarBatch; ++u) {
+          const bool in = tb + u < tf1;
+          const int64_t t = in ? tb + u : tf0;
+          const int R = ct_row[t];
+          const double *Tt = tiles + (int64_t)ct_slot[t] * 256;
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) {
+            const int row = 16 * R + 4 * kc + q;
+            ta[u][kc] = in ? Tt[(4 * kc + q) * 16 + c] : 0.0;   // A: T_RC(4kc + q, c)
+            vv[u][kc] = (row < B.n && colok) ? Vb[(int64_t)row * N + colj] : 0.0;   // B: V_R(4kc + q, colj)
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kFarBatch; ++u)
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) acc[j] = mfma64(-ta[u][kc], vv[u][kc], acc[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int C = C0 - j;
+      if (C < 0) break;
+      d4 a0 = acc[j], a1 = d4{0.0, 0.0, 0.0, 0.0};
+      const int64_t tn0 = cp[C], tn1 = cp[C + 1] - ct_nfar[B.rt0 + C];
+#pragma unroll
+      for (int u = 0; u < D; ++u) {
+        if (tn0 + u >= tn1) break;
+        const int R = ct_row[tn0 + u];
+        const double *Tt = tiles + (int64_t)ct_slot[tn0 + u] * 256 + q * 16 + c;
+        const double *vr = ring + (R % D) * 256 + 16 * q + c;   // B operand: V_R(4kc + q, c)
+        a0 = mfma64(-Tt[0], vr[0], a0);
+        a1 = mfma64(-Tt[128], vr[128], a1);
+        a0 = mfma64(-Tt[64], vr[64], a0);
+        a1 = mfma64(-Tt[192], vr[192], a1);
+      }
+      const d4 sum = a0 + a1;
+      const double *Ti = tinv + (B.rt0 + C) * 256 + q * 16 + c;
+      d4 out = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) out = mfma64(Ti[64 * kc], sum[kc], out);
+      wave_lds_sync();   // every read of the slot's previous tile (V_{C+D}) is done
+      double *slot = ring + (C % D) * 256 + 16 * q + c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        slot[64 * r] = out[r];
+        const int row = 16 * C + 4 * r + q;
+        if (colok && row < B.n) Vb[(int64_t)row * N + colj] = out[r];
+      }
+      wave_lds_sync();
+    }
+  }
+}
+
 // P = F^T D V (ldf x N per block); one wavefront per (block, 16 member columns,
 // chunk of up to 8 observation tiles).
 __global__ __launch_bounds__(64) void k_adj_ftdv(const Block *__restrict__ blocks, const int32_t *__restrict__ ot_jmax,
@@ -696,8 +794,25 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   phase_begin(p, ENKFMC_PH_BACKWARD, s);
   double *V = d.aux1;
   phase_begin(p, ENKFMC_PH_ADJ_SOLVE, s);
-  hipLaunchKernelGGL(k_adj_bwd_sweep, dim3(nb, ct), dim3(64), 0, s, d.blocks, d.ct_ptr, d.ct_row, d.ct_slot,
-                     d.fit_glob, d.interior_src, d.tiles, d.tinv, dXa, N, V);
+#define ADJ_BWD_NEAR(DD)                                                                                         \
+  hipLaunchKernelGGL(k_adj_bwd_sweep_near<DD>, dim3(nb * ct), dim3(64), 0, s, d.blocks, (int)ct, d.ct_ptr,        \
+                     d.ct_row, d.ct_slot, d.ct_nfar, d.fit_glob, d.interior_src, d.tiles, d.tinv, dXa, N, V)
+  if (p->near_d < std::max(1, (int)p->max_rt_back)) {   // far tiles exist: the split sweep
+    switch (p->near_d) {
+      case 1: ADJ_BWD_NEAR(1); break;
+      case 2: ADJ_BWD_NEAR(2); break;
+      case 3: ADJ_BWD_NEAR(3); break;
+      case 4: ADJ_BWD_NEAR(4); break;
+      case 5: ADJ_BWD_NEAR(5); break;
+      case 6: ADJ_BWD_NEAR(6); break;
+      case 7: ADJ_BWD_NEAR(7); break;
+      default: ADJ_BWD_NEAR(8); break;
+    }
+  } else {
+    hipLaunchKernelGGL(k_adj_bwd_sweep, dim3(nb, ct), dim3(64), 0, s, d.blocks, d.ct_ptr, d.ct_row, d.ct_slot,
+                       d.fit_glob, d.interior_src, d.tiles, d.tinv, dXa, N, V);
+  }
+#undef ADJ_BWD_NEAR
   if (p->max_bm > 0) {
     const unsigned ot = (unsigned)((p->max_bm + 15) / 16);
     hipLaunchKernelGGL(k_adj_ftdv, dim3(nb, ct, (ot + 7) / 8), dim3(64), 0, s, d.blocks, d.ot_jmax, d.F, d.dvec,

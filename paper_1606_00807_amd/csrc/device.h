@@ -20,7 +20,7 @@ struct Dev {
   const int64_t *o2b_ptr;
   const int32_t *o2b, *bobs_fit, *ot_jmax;
   const int64_t *rt_ptr, *ct_ptr;
-  const int32_t *rt_col, *rt_slot, *rt_nfar, *ct_row, *ct_slot;
+  const int32_t *rt_col, *rt_slot, *rt_nfar, *ct_row, *ct_slot, *ct_nfar;
   const uint16_t *tile_eoff;
   double *tiles, *tinv, *tdiag, *ubar;
   double *tval, *dvec, *mean, *U, *Z, *F, *S, *Q, *P, *W, *aux1, *aux2, *aux3, *dbar, *red;
@@ -53,6 +53,7 @@ inline Dev make_dev(enkfmc_plan *p) {
   d.rt_col = (const int32_t *)(w + L.rt_col);
   d.rt_slot = (const int32_t *)(w + L.rt_slot);
   d.rt_nfar = (const int32_t *)(w + L.rt_nfar);
+  d.ct_nfar = (const int32_t *)(w + L.ct_nfar);
   d.ct_ptr = (const int64_t *)(w + L.ct_ptr);
   d.ct_row = (const int32_t *)(w + L.ct_row);
   d.ct_slot = (const int32_t *)(w + L.ct_slot);

@@ -318,6 +318,14 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
           p->ct_slot[slot] = p->rt_slot[t];
         }
   }
+  p->ct_nfar.assign((size_t)p->n_rt, 0);
+  for (const Block &B : p->blocks)
+    for (int32_t C = 0; C < B.nrt; ++C) {
+      int32_t nf = 0;
+      for (int64_t t = p->ct_ptr[B.rt0 + C]; t < p->ct_ptr[B.rt0 + C + 1]; ++t)
+        if (p->ct_row[t] - C > p->near_d) ++nf;
+      p->ct_nfar[(size_t)(B.rt0 + C)] = nf;
+    }
   compute_layout(p);
   return ENKFMC_OK;
 }
@@ -350,6 +358,7 @@ void compute_layout(enkfmc_plan *p) {
   L.rt_col = take(p->rt_col.size() * 4);
   L.rt_slot = take(p->rt_slot.size() * 4);
   L.rt_nfar = take(p->rt_nfar.size() * 4 + 4);
+  L.ct_nfar = take(p->ct_nfar.size() * 4 + 4);
   L.ct_ptr = take((size_t)(p->n_rt + 1) * 8);
   L.ct_row = take(p->ct_row.size() * 4);
   L.ct_slot = take(p->ct_slot.size() * 4);

@@ -50,7 +50,7 @@ struct SubBox {
 struct Layout {
   size_t blocks, fit_glob, fit_blk, fit_rows, row_ptr, col, csc_ptr, csc_row, csc_nz, interior_src, bobs_o, bobs_row;
   size_t g2f_ptr, g2f, o2b_ptr, o2b, bobs_fit, ot_jmax;
-  size_t rt_ptr, rt_col, rt_slot, rt_nfar, ct_ptr, ct_row, ct_slot, tile_eoff;
+  size_t rt_ptr, rt_col, rt_slot, rt_nfar, ct_ptr, ct_row, ct_slot, ct_nfar, tile_eoff;
   size_t tval, dvec, mean, U, Z, F, S, Q, P, W, aux1, aux2, aux3, dbar, red, tiles, tinv, tdiag, ubar, pcg, status;
   size_t total;
 };
@@ -88,6 +88,7 @@ struct enkfmc_plan {
   std::vector<int32_t> rt_col, ct_row;          // tile indices inside the block
   std::vector<int32_t> rt_slot, ct_slot;        // dense tile slot
   std::vector<int32_t> rt_nfar;                 // per row tile: tiles with R - C > near_d (a prefix of its list)
+  std::vector<int32_t> ct_nfar;                 // per column tile: tiles with R - C > near_d (a suffix of its list)
   // per row tile rt and row i: at 16 (rt_ptr[rt] + rt + t) + i the offset, in
   // the row's CSR range, of its first entry in tile t of rt's list (t = number
   // of off-diagonal tiles: the diagonal tile); a row's entries are ascending,
