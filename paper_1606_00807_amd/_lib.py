@@ -107,6 +107,30 @@ def load(path: str = LIB_PATH):
     return lib
 
 
+def hip_stream_create() -> int:
+    """A new non-blocking HIP stream at the default priority, created by the
+    runtime the library is bound to; returns the raw hipStream_t."""
+    lib = load()
+    fn = lib.hipStreamCreateWithFlags
+    fn.restype, fn.argtypes = ctypes.c_int, [POINTER(c_void_p), ctypes.c_uint]
+    s = c_void_p()
+    err = fn(ctypes.byref(s), 1)  # hipStreamNonBlocking
+    if err != 0:
+        raise RuntimeError(f"hipStreamCreateWithFlags failed ({err})")
+    return int(s.value)
+
+
+def hip_stream_destroy(stream: int) -> None:
+    """Wait for the stream's work, then destroy it."""
+    lib = load()
+    sync, destroy = lib.hipStreamSynchronize, lib.hipStreamDestroy
+    for fn in (sync, destroy):
+        fn.restype, fn.argtypes = ctypes.c_int, [c_void_p]
+    err = sync(c_void_p(stream)) or destroy(c_void_p(stream))
+    if err != 0:
+        raise RuntimeError(f"destroying a HIP stream failed ({err})")
+
+
 def check(status: int) -> None:
     if status != ENKFMC_OK:
         msg = load().enkfmc_last_error().decode(errors="replace")

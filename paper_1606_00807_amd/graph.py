@@ -10,6 +10,11 @@ other; the branches run concurrently.  A device timestamp is written before
 an instance's first kernel and after its last, so each replay gives every
 instance's latency from the device clock.
 
+The branches run on streams of their own, created for the graph: streams
+taken from torch's pool may share a hardware queue with each other once
+the process has used many streams, and two branches on one queue run one
+after the other.
+
 This module only orders and captures library calls: the arithmetic is the
 library's.
 """
@@ -22,6 +27,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
+from ._lib import hip_stream_create, hip_stream_destroy
 from .api import Plan, timestamp, wall_clock_hz
 
 
@@ -48,7 +54,8 @@ class InstanceGraph:
             b = int(np.argmin(load))
             self.assign[b].append(k)
             load[b] += cost[k]
-        self.streams = [torch.cuda.Stream() for _ in range(self.branches)]
+        self._raw_streams = [hip_stream_create() for _ in range(self.branches)]
+        self.streams = [torch.cuda.ExternalStream(h) for h in self._raw_streams]
         self.Xa: List = [None] * n
         self.graph = None
 
@@ -106,6 +113,10 @@ class InstanceGraph:
         for it in self.items:
             it["plan"].set_async(False)
         self.graph = None
+        self.streams = []
+        for h in self._raw_streams:
+            hip_stream_destroy(h)
+        self._raw_streams = []
 
 
 def _tune_key(items: Sequence[Dict]) -> str:
