@@ -456,6 +456,175 @@ __global__ __launch_bounds__(64) void k_dual_Q(const Block *__restrict__ blocks,
   for (int a = m; a < lds; ++a) q[(int64_t)a * N + c] = 0.0;
 }
 
+// X = S^-1 V for one block and one tile of 16 members, from the Cholesky
+// factor L of S that k_dual_chol* leave in S (lower triangle, row stride
+// ldf): forward L Y = V, then backward L^T X = Y, by 16-row tiles.  The
+// products with the other tiles run on the matrix cores, their L operands
+// loaded straight from S (held in L2 for the block's member tiles, which are
+// neighbouring workgroups).  Inside a diagonal tile the 16 rows are taken in
+// turn from an LDS copy of the tile whose diagonal and upper part are zeroed,
+// 1/L_kk kept beside it.  Rows are permuted inside every tile: row 4q + r of
+// a tile sits at lane (q, c), register r (member c), and MFMA row rho = 4r + q
+// stands for it on both sides of every product, so a lane's A operands of
+// L_IJ are four consecutive doubles of one row.  Rows at or past m are zero
+// throughout (their loads masked), and rows m..ldf-1 of the result are
+// written as zeros.
+// MODE 0: V = Y^s - H X_b, X to Q (the analysis); MODE 1: V = Q, solved in
+// place (the reverse pass).
+constexpr int kSolveMaxTiles = 8;   // blocks of up to 128 observations
+
+// quarter_bcast with the row as an argument (a constant once the loops that
+// call it are unrolled)
+__device__ __forceinline__ double quarter_bcast_n(double v, int Q) {
+  switch (Q) {
+    case 0: return quarter_bcast<0>(v);
+    case 1: return quarter_bcast<1>(v);
+    case 2: return quarter_bcast<2>(v);
+    default: return quarter_bcast<3>(v);
+  }
+}
+
+template <int MODE, typename TX>
+__global__ __launch_bounds__(64) void k_solve_S_tiles(const Block *__restrict__ blocks, int G,
+                                                      const int32_t *__restrict__ bobs_o,
+                                                      const int32_t *__restrict__ bobs_row,
+                                                      const int32_t *__restrict__ fit_glob,
+                                                      const double *__restrict__ S, const double *__restrict__ Y,
+                                                      const TX *__restrict__ Xb, int64_t ld, int N,
+                                                      double *__restrict__ Q) {
+  __shared__ double dt[256];
+  __shared__ double dinv[16];
+  int b, g;
+  block_tile(G, b, g);
+  const Block B = blocks[b];
+  const int m = B.m;
+  if (m == 0) return;
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int pc = 4 * (c & 3) + (c >> 2);   // the tile row that MFMA row c stands for
+  const int col = 16 * g + c;
+  const bool cok = col < N;
+  const int TT = (m + 15) >> 4, ldf = B.ldf;
+  const double *L = S + B.S0;
+  double *Qb = Q + B.Q0;
+  d4 y[kSolveMaxTiles];
+#pragma unroll
+  for (int I = 0; I < kSolveMaxTiles; ++I) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = 16 * I + 4 * q + r;
+      double v = 0.0;
+      if (I < TT && a < m && cok) {
+        if constexpr (MODE == 0) {
+          const int o = bobs_o[B.obs0 + a];
+          const int64_t gl = fit_glob[B.row0 + bobs_row[B.obs0 + a]];
+          v = Y[(int64_t)o * N + col] - (double)Xb[gl * ld + col];
+        } else {
+          v = Qb[(int64_t)a * N + col];
+        }
+      }
+      y[I][r] = v;
+    }
+  }
+  // diagonal tile I to LDS: lane l takes row l >> 2, columns 4 (l & 3) .. + 3
+  auto stage = [&](int I) {
+    const int rr = lane >> 2, c0 = 4 * (lane & 3), ar = 16 * I + rr;
+    const double *src = L + (int64_t)ar * ldf + 16 * I + c0;
+    const double2 v01 = *(const double2 *)src, v23 = *(const double2 *)(src + 2);
+    const double vv[4] = {v01.x, v01.y, v23.x, v23.y};
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cc = c0 + j;
+      dt[rr * 16 + cc] = (cc < rr && ar < m) ? vv[j] : 0.0;
+      if (cc == rr) dinv[rr] = ar < m ? 1.0 / vv[j] : 1.0;
+    }
+    wave_lds_sync();
+  };
+  // forward: Y_I = L_II^-1 (V_I - sum_{J<I} L_IJ Y_J)
+#pragma unroll
+  for (int I = 0; I < kSolveMaxTiles; ++I) {
+    if (I < TT) {
+      d4 t = y[I];
+      const int arow = 16 * I + pc;
+      const bool rok = arow < m;
+#pragma unroll
+      for (int J = 0; J < I; ++J) {
+        const double *src = L + (int64_t)arow * ldf + 16 * J + 4 * q;
+        const double2 a01 = *(const double2 *)src, a23 = *(const double2 *)(src + 2);
+        t = mfma64(rok ? -a01.x : 0.0, y[J][0], t);
+        t = mfma64(rok ? -a01.y : 0.0, y[J][1], t);
+        t = mfma64(rok ? -a23.x : 0.0, y[J][2], t);
+        t = mfma64(rok ? -a23.y : 0.0, y[J][3], t);
+      }
+      stage(I);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {   // row k is final here: it sits at lanes q = k / 4, register k % 4
+        const double yk = quarter_bcast_n(t[k & 3] * dinv[k], k >> 2);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t[r] = fma(-dt[(4 * q + r) * 16 + k], yk, t[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) y[I][r] = t[r] * dinv[4 * q + r];
+    }
+  }
+  // backward: X_I = L_II^-T (Y_I - sum_{J>I} L_JI^T X_J)
+#pragma unroll
+  for (int I = kSolveMaxTiles - 1; I >= 0; --I) {
+    if (I < TT) {
+      d4 t = y[I];
+#pragma unroll
+      for (int J = I + 1; J < kSolveMaxTiles; ++J) {
+        if (J < TT) {
+          const double *src = L + (int64_t)(16 * J + 4 * q) * ldf + 16 * I + pc;
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) {
+            const double v = src[(int64_t)kc * ldf];
+            t = mfma64(16 * J + 4 * q + kc < m ? -v : 0.0, y[J][kc], t);
+          }
+        }
+      }
+      stage(I);
+#pragma unroll
+      for (int k = 15; k >= 0; --k) {
+        const double xk = quarter_bcast_n(t[k & 3] * dinv[k], k >> 2);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t[r] = fma(-dt[k * 16 + 4 * q + r], xk, t[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) y[I][r] = t[r] * dinv[4 * q + r];
+    }
+  }
+  if (cok) {
+#pragma unroll
+    for (int I = 0; I < kSolveMaxTiles; ++I)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * I + 4 * q + r;
+        if (a < ldf) Qb[(int64_t)a * N + col] = I < TT ? y[I][r] : 0.0;
+      }
+  }
+}
+
+template <typename TX>
+static void launch_solve_S(enkfmc_plan *p, const Dev &d, int mode, const TX *Xb, int64_t ld, const double *Y,
+                           double *Q, hipStream_t s) {
+  const int G = (p->N + 15) / 16;
+  const dim3 grid((unsigned)(p->blocks.size() * G));
+  if (mode == 0)
+    hipLaunchKernelGGL((k_solve_S_tiles<0, TX>), grid, dim3(64), 0, s, d.blocks, G, d.bobs_o, d.bobs_row, d.fit_glob,
+                       d.S, Y, Xb, ld, p->N, Q);
+  else
+    hipLaunchKernelGGL((k_solve_S_tiles<1, TX>), grid, dim3(64), 0, s, d.blocks, G, d.bobs_o, d.bobs_row, d.fit_glob,
+                       d.S, Y, Xb, ld, p->N, Q);
+}
+
+bool solve_S_tiles_fit(const enkfmc_plan *p) { return p->max_bm <= 16 * kSolveMaxTiles; }
+
+hipError_t launch_adj_solve_S_tiles(enkfmc_plan *p, const Dev &d, double *P, hipStream_t s) {
+  launch_solve_S<double>(p, d, 1, nullptr, 0, nullptr, P, s);
+  return hipGetLastError();
+}
+
 // G = D (F Q) of row tile R (or D (V - F Q) with V given), written into the
 // output rows that the forward sweep then solves in place.  One wavefront per
 // (block, row tile).  Each F fragment it loads feeds up to kGTiles 16-member
@@ -960,8 +1129,11 @@ static hipError_t analysis_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
   if (e != hipSuccess) return e;
   if (p->max_bm > 0) {
     phase_begin(p, ENKFMC_PH_DUAL_Q, s);
-    hipLaunchKernelGGL(k_dual_Q<TX>, dim3(nb, (N + 63) / 64), dim3(64), 0, s, d.blocks, d.bobs_o, d.bobs_row,
-                       d.fit_glob, d.S, Y, Xb, ld, N, d.Q);
+    if (solve_S_tiles_fit(p))
+      launch_solve_S<TX>(p, d, 0, Xb, ld, Y, d.Q, s);
+    else
+      hipLaunchKernelGGL(k_dual_Q<TX>, dim3(nb, (N + 63) / 64), dim3(64), 0, s, d.blocks, d.bobs_o, d.bobs_row,
+                         d.fit_glob, d.S, Y, Xb, ld, N, d.Q);
     phase_end(p, ENKFMC_PH_DUAL_Q, s);
   }
   e = launch_fwd_sweep(p, d, d.Q, nullptr, d.Z, s);

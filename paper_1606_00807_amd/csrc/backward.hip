@@ -817,7 +817,12 @@ static hipError_t backward_typed(enkfmc_plan *p, const Dev &d, const TX *Xb, int
     const unsigned ot = (unsigned)((p->max_bm + 15) / 16);
     hipLaunchKernelGGL(k_adj_ftdv, dim3(nb, ct, (ot + 7) / 8), dim3(64), 0, s, d.blocks, d.ot_jmax, d.F, d.dvec,
                        (const double *)V, N, d.P);
-    hipLaunchKernelGGL(k_adj_solve_S, dim3(nb, (N + 63) / 64), dim3(64), 0, s, d.blocks, d.S, N, d.P);
+    if (solve_S_tiles_fit(p)) {
+      const hipError_t es = launch_adj_solve_S_tiles(p, d, d.P, s);
+      if (es != hipSuccess) return es;
+    } else {
+      hipLaunchKernelGGL(k_adj_solve_S, dim3(nb, (N + 63) / 64), dim3(64), 0, s, d.blocks, d.S, N, d.P);
+    }
   }
   hipError_t e = launch_fwd_sweep(p, d, d.P, V, d.W, s);
   if (e != hipSuccess) return e;

@@ -98,6 +98,24 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Row Q of the wavefront (lanes 16Q..16Q+15), given to all four rows, lane
+// 16q + c receiving lane 16Q + c.  With rows written (r0, r1, r2, r3): the
+// 16-lane swap of the low and high words (lo, hi) leaves (lo0, hi0, lo2, hi2)
+// in its first result and (lo1, hi1, lo3, hi3) in its second; the 32-lane swap
+// of one of them with itself leaves (loQ, hiQ, loQ, hiQ) in one result; the
+// 16-lane swap of that with itself leaves loQ in all rows of its first result
+// and hiQ in all rows of its second.
+template <int Q>
+__device__ __forceinline__ double quarter_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto s1 = __builtin_amdgcn_permlane16_swap((unsigned)(b & 0xffffffffll), (unsigned)(b >> 32), false, false);
+  const unsigned t = (Q & 1) ? s1[1] : s1[0];
+  const auto s2 = __builtin_amdgcn_permlane32_swap(t, t, false, false);
+  const unsigned u = (Q & 2) ? s2[1] : s2[0];
+  const auto s3 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  return __longlong_as_double(((long long)s3[1] << 32) | s3[0]);
+}
+
 // First error wins; status[1] records where it happened.
 // MI355X dispatches the workgroups of a launch to its 8 XCDs in turn
 // (workgroup b to XCD b mod 8), and each XCD has an L2 of its own.  This maps
@@ -228,6 +246,10 @@ hipError_t launch_analysis_pcg(enkfmc_plan *p, const Dev &d, const void *Xb, int
                                const double *Y, const double *r_diag, hipStream_t s, int32_t *converged);
 hipError_t pcg_column_stats(enkfmc_plan *p, hipStream_t s, int32_t *max_iter, double *max_rel);
 hipError_t launch_dual_factor(enkfmc_plan *p, const Dev &d, const double *r_diag, hipStream_t s);
+// P <- S^-1 P by 16-row tiles with the factor the analysis left in S, for
+// plans whose blocks hold at most 128 observations (solve_S_tiles_fit)
+bool solve_S_tiles_fit(const enkfmc_plan *p);
+hipError_t launch_adj_solve_S_tiles(enkfmc_plan *p, const Dev &d, double *P, hipStream_t s);
 hipError_t launch_mapback(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, void *Xa,
                           int32_t out_dtype, hipStream_t s);
 hipError_t launch_analysis_dual(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld,

@@ -148,24 +148,6 @@ __device__ __forceinline__ double row_bcast(double v) {
   return __longlong_as_double(__builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x150 + N, 0xf, 0xf, true));
 }
 
-// Row Q of the wavefront (lanes 16Q..16Q+15), given to all four rows, lane
-// 16q + c receiving lane 16Q + c.  With rows written (r0, r1, r2, r3): the
-// 16-lane swap of the low and high words (lo, hi) leaves (lo0, hi0, lo2, hi2)
-// in its first result and (lo1, hi1, lo3, hi3) in its second; the 32-lane swap
-// of one of them with itself leaves (loQ, hiQ, loQ, hiQ) in one result; the
-// 16-lane swap of that with itself leaves loQ in all rows of its first result
-// and hiQ in all rows of its second.
-template <int Q>
-__device__ __forceinline__ double quarter_bcast(double v) {
-  const long long b = __double_as_longlong(v);
-  const auto s1 = __builtin_amdgcn_permlane16_swap((unsigned)(b & 0xffffffffll), (unsigned)(b >> 32), false, false);
-  const unsigned t = (Q & 1) ? s1[1] : s1[0];
-  const auto s2 = __builtin_amdgcn_permlane32_swap(t, t, false, false);
-  const unsigned u = (Q & 2) ? s2[1] : s2[0];
-  const auto s3 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-  return __longlong_as_double(((long long)s3[1] << 32) | s3[0]);
-}
-
 // Sum over the four rows of 16 lanes (lanes c, c + 16, c + 32, c + 48), each
 // of them receiving it.  Swapping a register with itself across 16 lanes
 // leaves rows (0, 0, 2, 2) and (1, 1, 3, 3), so their sum holds r0 + r1 and
