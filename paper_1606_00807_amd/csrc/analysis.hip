@@ -351,7 +351,8 @@ __global__ __launch_bounds__(64) void k_dual_S(const Block *__restrict__ blocks,
   }
 }
 
-// In-place Cholesky of each block's S (m x m lower part, stride ldf), one workgroup per block.
+// In-place Cholesky of each block's S (m x m lower part, stride ldf), one
+// workgroup per block: blocks of more than 128 observations.
 __global__ __launch_bounds__(256) void k_dual_chol(const Block *__restrict__ blocks, double *__restrict__ S,
                                                    int32_t *status) {
   __shared__ int bad;
@@ -380,58 +381,6 @@ __global__ __launch_bounds__(256) void k_dual_chol(const Block *__restrict__ blo
       if (j <= i) L[(int64_t)i * ld + j] -= L[(int64_t)i * ld + k] * L[(int64_t)j * ld + k];
     }
   }
-}
-
-// The same factorisation with the block's lower triangle packed in LDS (row i
-// at i(i+1)/2), left-looking: for column j the thread of row i >= j forms
-// S_ij - sum_{k<j} L_ik L_jk in four partial sums, every thread also forms the
-// pivot S_jj - sum_k L_jk^2, and one barrier per column publishes the column.
-// For blocks of up to kCholLdsMax observations (the triangle fits 64 KB).
-constexpr int kCholLdsMax = 126;
-constexpr int kCholThreads = 128;
-
-__device__ inline double packed_dot(const double *__restrict__ a, const double *__restrict__ b, int n) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int k = 0;
-  for (; k + 4 <= n; k += 4) {
-    s0 = fma(a[k], b[k], s0);
-    s1 = fma(a[k + 1], b[k + 1], s1);
-    s2 = fma(a[k + 2], b[k + 2], s2);
-    s3 = fma(a[k + 3], b[k + 3], s3);
-  }
-  for (; k < n; ++k) s0 = fma(a[k], b[k], s0);
-  return (s0 + s1) + (s2 + s3);
-}
-
-__global__ __launch_bounds__(kCholThreads) void k_dual_chol_lds(const Block *__restrict__ blocks,
-                                                               double *__restrict__ S, int32_t *status) {
-  extern __shared__ double P[];
-  const Block B = blocks[blockIdx.x];
-  const int m = B.m, ld = B.ldf, tid = threadIdx.x;
-  double *L = S + B.S0;
-#pragma unroll 4
-  for (int i = 0; i < m; ++i)
-    for (int j = tid; j <= i; j += kCholThreads) P[i * (i + 1) / 2 + j] = L[(int64_t)i * ld + j];
-  __syncthreads();
-  for (int j = 0; j < m; ++j) {
-    const double *rj = P + j * (j + 1) / 2;
-    const double d = rj[j] - packed_dot(rj, rj, j);
-    if (!(d > 0.0)) {
-      if (tid == 0) set_error(status, ENKFMC_ENOTSPD, -1 - (int32_t)blockIdx.x);
-      return;   // d is the same in every thread: all leave together
-    }
-    const double ljj = sqrt(d);
-    for (int i = j + 1 + tid; i < m; i += kCholThreads) {
-      double *ri = P + i * (i + 1) / 2;
-      ri[j] = (ri[j] - packed_dot(ri, rj, j)) / ljj;
-    }
-    __syncthreads();   // column j of L below the diagonal is in place
-    if (tid == 0) P[j * (j + 1) / 2 + j] = ljj;
-  }
-  __syncthreads();
-#pragma unroll 4
-  for (int i = 0; i < m; ++i)
-    for (int j = tid; j <= i; j += kCholThreads) L[(int64_t)i * ld + j] = P[i * (i + 1) / 2 + j];
 }
 
 // Q = S^-1 Delta, one lane per member column; rows m..ldf-1 of Q are zeroed.
@@ -1087,11 +1036,12 @@ hipError_t launch_dual_factor(enkfmc_plan *p, const Dev &d, const double *r_diag
                        d.dvec, r_diag, d.S);
     phase_end(p, ENKFMC_PH_DUAL_S, s);
     phase_begin(p, ENKFMC_PH_DUAL_CHOL, s);
-    if (p->max_bm <= kCholLdsMax)
-      hipLaunchKernelGGL(k_dual_chol_lds, dim3(nb), dim3(kCholThreads),
-                         (size_t)p->max_bm * (p->max_bm + 1) / 2 * sizeof(double), s, d.blocks, d.S, d.status);
-    else
+    if (dual_chol_tiles_fit(p)) {
+      const hipError_t e = launch_dual_chol_tiles(p, d, s);
+      if (e != hipSuccess) return e;
+    } else {
       hipLaunchKernelGGL(k_dual_chol, dim3(nb), dim3(256), 0, s, d.blocks, d.S, d.status);
+    }
     phase_end(p, ENKFMC_PH_DUAL_CHOL, s);
   }
   return hipGetLastError();

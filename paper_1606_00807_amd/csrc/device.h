@@ -249,6 +249,10 @@ hipError_t launch_dual_factor(enkfmc_plan *p, const Dev &d, const double *r_diag
 // P <- S^-1 P by 16-row tiles with the factor the analysis left in S, for
 // plans whose blocks hold at most 128 observations (solve_S_tiles_fit)
 bool solve_S_tiles_fit(const enkfmc_plan *p);
+// Cholesky of every block's S by 16 x 16 register tiles, one wavefront per
+// block, for plans whose blocks hold at most 128 observations
+bool dual_chol_tiles_fit(const enkfmc_plan *p);
+hipError_t launch_dual_chol_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s);
 hipError_t launch_adj_solve_S_tiles(enkfmc_plan *p, const Dev &d, double *P, hipStream_t s);
 hipError_t launch_mapback(enkfmc_plan *p, const Dev &d, const void *Xb, int32_t dtype, int64_t ld, void *Xa,
                           int32_t out_dtype, hipStream_t s);

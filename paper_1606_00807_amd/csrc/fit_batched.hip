@@ -273,6 +273,88 @@ __device__ __forceinline__ void adj_pre_kf(const int lane, const int64_t r, cons
 // both products multiply by the vector's entry c and sum over the row of 16
 // lanes; the four sums of a row go in one exchange (row16_sum4), which leaves
 // entry 4(c/4) + q in lane (q, c).
+// Blocked Cholesky of a symmetric matrix of T 16 x 16 tiles held in
+// registers (step 3 of fit_row).  Lane (q, c) holds, in register rr of
+// acc[tix(I, J)] (I >= J), element (4rr + q, c) of A_IJ^T.  Per panel J the
+// 16 columns of the diagonal tile are eliminated one at a time, carrying an
+// identity tile E along as extra rows, so that E ends as L_JJ^-T; the tiles
+// below then follow as L_IJ = A_IJ L_JJ^-T by MFMA, and the trailing tiles
+// take their updates.  Each column's values reach the other lanes by
+// cross-lane moves (elim_col).  Columns stay unscaled during the elimination:
+// the update uses a[i][k] a[j][k] / piv_k, and at the end each column c is
+// scaled once by its 1/L_cc, which also turns its final pivot into L_cc.
+// On return acc[tix(I, J)] holds L_IJ^T below the diagonal and L_JJ^-T on it.
+// BORDER: a bordering row (entry 16J + c at lane (0, c) of augv[J]) is
+// eliminated along and leaves as L^-1 of it; tba is 16 doubles of LDS for it.
+// diag_out(J, L_JJ) receives each diagonal tile of the factor as its panel
+// is done (element (4rr + q, c) in register rr; only entries with
+// 4rr + q >= c are meaningful).  False at the first pivot that is not
+// positive (or NaN).
+struct NoDiagOut {
+  __device__ void operator()(int, const d4 &) const {}
+};
+template <int T, bool BORDER, typename DiagOut>
+__device__ __forceinline__ bool chol_tiles(const int q, const int c, d4 (&acc)[T * (T + 1) / 2], double (&augv)[T],
+                                           double *tba, const DiagOut &diag_out) {
+#pragma unroll
+  for (int J = 0; J < T; ++J) {
+    const bool below = J + 1 < T;
+    d4 eid;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) eid[rr] = (4 * rr + q == c) ? 1.0 : 0.0;
+    // pivot of the panel's first column (after the trailing updates)
+    double piv = readlane_d(acc[tix<T>(J, J)][0], 0);
+    double myinv = 0.0;
+    if (!elim_cols<0>(c, acc[tix<T>(J, J)], eid, augv[J], piv, myinv)) return false;
+    if constexpr (BORDER) augv[J] *= myinv;
+    diag_out(J, acc[tix<T>(J, J)] * myinv);
+    eid *= myinv;   // L_JJ^-T; the accumulator layout is the B operand layout
+    // L_JJ itself is not needed again: its slot keeps L_JJ^-T
+    acc[tix<T>(J, J)] = eid;
+    if (below) {
+      // L_IJ^T = L_JJ^-1 A_IJ^T: E's registers as the A operand give E^T =
+      // L_JJ^-1, and the stored A_IJ^T is the B operand of its own registers.
+#pragma unroll
+      for (int I = J + 1; I < T; ++I) {
+        d4 a = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) a = mfma64(eid[kc], acc[tix<T>(I, J)][kc], a);
+        acc[tix<T>(I, J)] = a;
+      }
+      // Trailing update, kept transposed: A_{I,I2}^T -= L_{I2,J} L_{I,J}^T, the
+      // A operand from the registers of L_{I2,J}^T (negated once) and the B
+      // operand those of L_{I,J}^T.  The bordering row enters as row 0 of an A
+      // operand, through LDS.
+      if constexpr (BORDER) {
+        if (q == 0) tba[c] = augv[J];
+        wave_lds_sync();
+      }
+#pragma unroll
+      for (int I2 = J + 1; I2 < T; ++I2) {
+        const d4 ny = -acc[tix<T>(I2, J)];
+#pragma unroll
+        for (int I = I2; I < T; ++I) {
+          d4 a = acc[tix<T>(I, I2)];
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) a = mfma64(ny[kc], acc[tix<T>(I, J)][kc], a);
+          acc[tix<T>(I, I2)] = a;
+        }
+        if constexpr (BORDER) {
+          d4 a = d4{augv[I2], 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) {
+            const double tv = tba[4 * kc + q];   // read by every lane, used at c = 0
+            a = mfma64(c == 0 ? tv : 0.0, ny[kc], a);
+          }
+          augv[I2] = a[0];
+        }
+      }
+      if constexpr (BORDER) wave_lds_sync();
+    }
+  }
+  return true;
+}
+
 template <int T>
 __device__ __forceinline__ void back_subst(const int q, const int c, const d4 (&acc)[T * (T + 1) / 2],
                                            const double (&yr)[T], double *y) {
@@ -576,68 +658,9 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   }
 
   // ---- 3. blocked Cholesky of the bordered matrix -------------------------
-  // Per panel J: the 16 columns of the diagonal tile are eliminated one at a
-  // time, carrying an identity tile E along as extra rows, so that E ends as
-  // L_JJ^-T; the tiles below then follow as L_IJ = A_IJ L_JJ^-T by MFMA.
-  // Each column's values reach the other lanes by cross-lane moves
-  // (elim_col).  Columns stay unscaled during the elimination: the update uses
-  // a[i][k] a[j][k] / piv_k.  At the end each column c is scaled once by its
-  // 1/L_cc, which also turns its final pivot into L_cc.  A pivot that is not
-  // positive (or NaN) ends the row with an error.
-#pragma unroll
-  for (int J = 0; J < T; ++J) {
-    const bool below = J + 1 < T;
-    d4 eid;
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) eid[rr] = (4 * rr + q == c) ? 1.0 : 0.0;
-    // pivot of the panel's first column (after the trailing updates)
-    double piv = readlane_d(acc[tix<T>(J, J)][0], 0);
-    double myinv = 0.0;
-    if (!elim_cols<0>(c, acc[tix<T>(J, J)], eid, augv[J], piv, myinv)) {
-      if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
-      return;
-    }
-    augv[J] *= myinv;
-    eid *= myinv;   // L_JJ^-T; the accumulator layout is the B operand layout
-    // L_JJ itself is not needed again: its slot keeps L_JJ^-T for step 4
-    acc[tix<T>(J, J)] = eid;
-    if (below) {
-      // L_IJ^T = L_JJ^-1 A_IJ^T: E's registers as the A operand give E^T =
-      // L_JJ^-1, and the stored A_IJ^T is the B operand of its own registers.
-#pragma unroll
-      for (int I = J + 1; I < T; ++I) {
-        d4 a = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc) a = mfma64(eid[kc], acc[tix<T>(I, J)][kc], a);
-        acc[tix<T>(I, J)] = a;
-      }
-      // Trailing update, kept transposed: A_{I,I2}^T -= L_{I2,J} L_{I,J}^T, the
-      // A operand from the registers of L_{I2,J}^T (negated once) and the B
-      // operand those of L_{I,J}^T.  The bordering row enters as row 0 of an A
-      // operand, through LDS.
-      double *tba = L.tile;
-      if (q == 0) tba[c] = augv[J];
-      wave_lds_sync();
-#pragma unroll
-      for (int I2 = J + 1; I2 < T; ++I2) {
-        const d4 ny = -acc[tix<T>(I2, J)];
-#pragma unroll
-        for (int I = I2; I < T; ++I) {
-          d4 a = acc[tix<T>(I, I2)];
-#pragma unroll
-          for (int kc = 0; kc < 4; ++kc) a = mfma64(ny[kc], acc[tix<T>(I, J)][kc], a);
-          acc[tix<T>(I, I2)] = a;
-        }
-        d4 a = d4{augv[I2], 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-          const double tv = tba[4 * kc + q];   // read by every lane, used at c = 0
-          a = mfma64(c == 0 ? tv : 0.0, ny[kc], a);
-        }
-        augv[I2] = a[0];
-      }
-      wave_lds_sync();
-    }
+  if (!chol_tiles<T, true>(q, c, acc, augv, L.tile, NoDiagOut{})) {
+    if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
+    return;
   }
 
   // the factored tiles to the cache slot (fit with a factor cache)
@@ -1309,6 +1332,75 @@ __global__ __launch_bounds__(256) void k_fit_p0(const int32_t *__restrict__ fit_
 bool fit_writes_tiles(const enkfmc_plan *p) {
   return p->bucket_off[kBucketPlain + 1] == p->bucket_off[kBucketPlain] && (int64_t)p->n_slots < (1ll << 23) &&
          (int64_t)p->n_rt < (1ll << 23);
+}
+
+// Cholesky factor of one block's S = R + F^T D F (up to 128 observations) by
+// chol_tiles, one wavefront per block.  The lower triangle of S loads into
+// the registers as chol_tiles expects them (tile (I, J) transposed; the
+// diagonal tiles from their lower halves, mirrored), entries at or past row
+// or column m as the identity; the factor goes back to S in its natural
+// layout: L_IJ from the factored tiles, L_JJ as the diagonal tiles leave the
+// elimination.
+template <int T>
+__device__ __forceinline__ bool dual_chol_block(const int q, const int c, const Block &B, double *__restrict__ S) {
+  constexpr int NT = T * (T + 1) / 2;
+  const int m = B.m;
+  const int64_t ldf = B.ldf;
+  double *L = S + B.S0;
+  d4 acc[NT];
+#pragma unroll
+  for (int I = 0; I < T; ++I)
+#pragma unroll
+    for (int J = 0; J <= I; ++J)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int i = 16 * I + c, j = 16 * J + 4 * rr + q;   // element (4rr + q, c) of A_IJ^T is A[i][j]
+        const int hi = i > j ? i : j, lo = i > j ? j : i;
+        const double v = L[hi * ldf + lo];
+        acc[tix<T>(I, J)][rr] = (hi < m) ? v : (i == j ? 1.0 : 0.0);
+      }
+  double augv[T];
+#pragma unroll
+  for (int J = 0; J < T; ++J) augv[J] = 0.0;
+  const auto diag_out = [&](int J, const d4 &t) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+      if (4 * rr + q >= c) L[(16 * J + 4 * rr + q) * ldf + 16 * J + c] = t[rr];
+  };
+  if (!chol_tiles<T, false>(q, c, acc, augv, nullptr, diag_out)) return false;
+#pragma unroll
+  for (int I = 1; I < T; ++I)
+#pragma unroll
+    for (int J = 0; J < I; ++J)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) L[(16 * I + c) * ldf + 16 * J + 4 * rr + q] = acc[tix<T>(I, J)][rr];
+  return true;
+}
+
+__global__ __launch_bounds__(64, 1) void k_dual_chol_tiles(const Block *__restrict__ blocks, double *__restrict__ S,
+                                                          int32_t *status) {
+  const Block B = blocks[blockIdx.x];
+  if (B.m == 0) return;
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  bool ok;
+  switch ((B.m + 15) >> 4) {
+    case 1: ok = dual_chol_block<1>(q, c, B, S); break;
+    case 2: ok = dual_chol_block<2>(q, c, B, S); break;
+    case 3: ok = dual_chol_block<3>(q, c, B, S); break;
+    case 4: ok = dual_chol_block<4>(q, c, B, S); break;
+    case 5: ok = dual_chol_block<5>(q, c, B, S); break;
+    case 6: ok = dual_chol_block<6>(q, c, B, S); break;
+    case 7: ok = dual_chol_block<7>(q, c, B, S); break;
+    default: ok = dual_chol_block<8>(q, c, B, S); break;
+  }
+  if (!ok && lane == 0) set_error(status, ENKFMC_ENOTSPD, -1 - (int32_t)blockIdx.x);
+}
+
+bool dual_chol_tiles_fit(const enkfmc_plan *p) { return p->max_bm <= 16 * kMaxT; }
+
+hipError_t launch_dual_chol_tiles(enkfmc_plan *p, const Dev &d, hipStream_t s) {
+  hipLaunchKernelGGL(k_dual_chol_tiles, dim3((unsigned)p->blocks.size()), dim3(64), 0, s, d.blocks, d.S, d.status);
+  return hipGetLastError();
 }
 
 static TileOut tile_out(const enkfmc_plan *p, const Dev &d) {
