@@ -205,13 +205,17 @@ __device__ __forceinline__ void elim_col(const int c, d4 &ajj, d4 &eid, double &
   ag = fma(-ab, cv1, ag);   // entries c <= K stay as they are (cv1 = 0)
 }
 
-// Columns K..15; false at the first pivot that is not positive (or NaN).
+// Columns K..kend-1 (kend <= 16: the tile's columns that belong to the
+// system; those past it are padding, coupled to nothing, and are left
+// alone, their 1/L_cc staying 0); false at the first pivot that is not
+// positive (or NaN).
 template <int K>
 __device__ __forceinline__ bool elim_cols(const int c, d4 &ajj, d4 &eid, double &ag,
-                                          double &piv, double &myinv) {
+                                          double &piv, double &myinv, const int kend) {
+  if (K >= kend) return true;
   if (!(piv > 0.0)) return false;
   elim_col<K>(c, ajj, eid, ag, piv, myinv);
-  if constexpr (K + 1 < 16) return elim_cols<K + 1>(c, ajj, eid, ag, piv, myinv);
+  if constexpr (K + 1 < 16) return elim_cols<K + 1>(c, ajj, eid, ag, piv, myinv, kend);
   return true;
 }
 
@@ -274,7 +278,8 @@ __device__ __forceinline__ void adj_pre_kf(const int lane, const int64_t r, cons
 // lanes; the four sums of a row go in one exchange (row16_sum4), which leaves
 // entry 4(c/4) + q in lane (q, c).
 // Blocked Cholesky of a symmetric matrix of T 16 x 16 tiles held in
-// registers (step 3 of fit_row).  Lane (q, c) holds, in register rr of
+// registers (step 3 of fit_row), of which the first m rows and columns are
+// the system and the rest (past m, in the last tile) an identity padding.  Lane (q, c) holds, in register rr of
 // acc[tix(I, J)] (I >= J), element (4rr + q, c) of A_IJ^T.  Per panel J the
 // 16 columns of the diagonal tile are eliminated one at a time, carrying an
 // identity tile E along as extra rows, so that E ends as L_JJ^-T; the tiles
@@ -283,7 +288,9 @@ __device__ __forceinline__ void adj_pre_kf(const int lane, const int64_t r, cons
 // cross-lane moves (elim_col).  Columns stay unscaled during the elimination:
 // the update uses a[i][k] a[j][k] / piv_k, and at the end each column c is
 // scaled once by its 1/L_cc, which also turns its final pivot into L_cc.
-// On return acc[tix(I, J)] holds L_IJ^T below the diagonal and L_JJ^-T on it.
+// On return acc[tix(I, J)] holds L_IJ^T below the diagonal and L_JJ^-T on it,
+// with zeros in the padding's columns of L_JJ^-T (the padding is not
+// eliminated), so that solves with these tiles leave zeros there.
 // BORDER: a bordering row (entry 16J + c at lane (0, c) of augv[J]) is
 // eliminated along and leaves as L^-1 of it; tba is 16 doubles of LDS for it.
 // diag_out(J, L_JJ) receives each diagonal tile of the factor as its panel
@@ -294,8 +301,8 @@ struct NoDiagOut {
   __device__ void operator()(int, const d4 &) const {}
 };
 template <int T, bool BORDER, typename DiagOut>
-__device__ __forceinline__ bool chol_tiles(const int q, const int c, d4 (&acc)[T * (T + 1) / 2], double (&augv)[T],
-                                           double *tba, const DiagOut &diag_out) {
+__device__ __forceinline__ bool chol_tiles(const int q, const int c, const int m, d4 (&acc)[T * (T + 1) / 2],
+                                           double (&augv)[T], double *tba, const DiagOut &diag_out) {
 #pragma unroll
   for (int J = 0; J < T; ++J) {
     const bool below = J + 1 < T;
@@ -305,7 +312,9 @@ __device__ __forceinline__ bool chol_tiles(const int q, const int c, d4 (&acc)[T
     // pivot of the panel's first column (after the trailing updates)
     double piv = readlane_d(acc[tix<T>(J, J)][0], 0);
     double myinv = 0.0;
-    if (!elim_cols<0>(c, acc[tix<T>(J, J)], eid, augv[J], piv, myinv)) return false;
+    // only the last tile can hold padding (T = ceil(m / 16))
+    const int kend = J + 1 < T ? 16 : m - 16 * J;
+    if (!elim_cols<0>(c, acc[tix<T>(J, J)], eid, augv[J], piv, myinv, kend)) return false;
     if constexpr (BORDER) augv[J] *= myinv;
     diag_out(J, acc[tix<T>(J, J)] * myinv);
     eid *= myinv;   // L_JJ^-T; the accumulator layout is the B operand layout
@@ -658,7 +667,7 @@ __device__ __forceinline__ void fit_row(const int lane, const int64_t r, const i
   }
 
   // ---- 3. blocked Cholesky of the bordered matrix -------------------------
-  if (!chol_tiles<T, true>(q, c, acc, augv, L.tile, NoDiagOut{})) {
+  if (!chol_tiles<T, true>(q, c, m, acc, augv, L.tile, NoDiagOut{})) {
     if (lane == 0) set_error(status, ENKFMC_ENOTSPD, (int32_t)r);
     return;
   }
@@ -1367,7 +1376,7 @@ __device__ __forceinline__ bool dual_chol_block(const int q, const int c, const 
     for (int rr = 0; rr < 4; ++rr)
       if (4 * rr + q >= c) L[(16 * J + 4 * rr + q) * ldf + 16 * J + c] = t[rr];
   };
-  if (!chol_tiles<T, false>(q, c, acc, augv, nullptr, diag_out)) return false;
+  if (!chol_tiles<T, false>(q, c, m, acc, augv, nullptr, diag_out)) return false;
 #pragma unroll
   for (int I = 1; I < T; ++I)
 #pragma unroll
