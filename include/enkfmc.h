@@ -110,6 +110,12 @@ typedef struct {
   int64_t f_entries;       /* entries of the dual form's F = T^-T H^T, all blocks     */
   int64_t s_entries;       /* entries of its S = R + F^T D F, all blocks              */
   size_t factor_cache_bytes; /* memory enkfmc_plan_set_factor_cache needs      */
+  /* Row-tile distances R - C of the stored tiles T_RC (C < R) of T, which
+   * decide the form of the triangular sweeps: every distance 1..near_d
+   * occurs (at most 8); far_lo is the smallest distance beyond near_d (0 if
+   * none), max_tile_distance the largest, and far_ring the widest range of
+   * distances beyond near_d within one block.                              */
+  int32_t near_d, far_lo, max_tile_distance, far_ring;
 } enkfmc_plan_info;
 
 /* Build the decomposition of Section 3 (host only, no device work).

@@ -35,7 +35,8 @@ class PlanInfo(ctypes.Structure):
                 ("max_block_rows", c_int32), ("max_block_obs", c_int32), ("reserved", c_int32),
                 ("workspace_bytes", c_size_t), ("fit_rows_wave", c_int64), ("fit_rows_plain", c_int64),
                 ("n_row_tiles", c_int64), ("n_tiles", c_int64), ("f_entries", c_int64), ("s_entries", c_int64),
-                ("factor_cache_bytes", c_size_t)]
+                ("factor_cache_bytes", c_size_t), ("near_d", c_int32), ("far_lo", c_int32),
+                ("max_tile_distance", c_int32), ("far_ring", c_int32)]
 
 
 class EnkfmcError(RuntimeError):

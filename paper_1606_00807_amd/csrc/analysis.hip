@@ -916,6 +916,128 @@ __global__ __launch_bounds__(64) void k_fwd_sweep_near(const Block *__restrict__
   }
 }
 
+// The forward sweep with a ring of only the Z tiles that stored tiles reach:
+// the near run of distances 1..D (slot C mod D) and the block's far range
+// lo..hi (slot C mod Wf, Wf = hi - lo + 1, from the planner), leaving out the
+// distances between them, which none of the block's tiles has.  Each product reads its Z tile from LDS.  At the
+// end of row tile R the tile entering the far range, Z_{R+1-lo}, goes into
+// its slot: from the near ring when lo = D + 1 (it is the tile Z_R is about
+// to replace), otherwise from memory, where this wavefront wrote it at least
+// two row tiles earlier.  So each Z tile comes back from memory at most once,
+// where the split sweep reads it once per far tile that uses it.  A row
+// tile's T tiles load together, kGapBatch at a time; G, the inverse diagonal
+// tile and the far entry of the next row tile load one row tile ahead.  One
+// wavefront per (block, member tile), numbered so that the member tiles of a
+// block share its T tiles in L2.
+constexpr int kGapBatch = 12;
+constexpr size_t kGapRingMaxBytes = 32 * 1024;
+
+template <int D>
+__global__ __launch_bounds__(64) void k_fwd_sweep_gap(const Block *__restrict__ blocks, int ng,
+                                                      const int64_t *__restrict__ rt_ptr,
+                                                      const int32_t *__restrict__ rt_col,
+                                                      const int32_t *__restrict__ rt_slot,
+                                                      const double *__restrict__ tiles,
+                                                      const double *__restrict__ tinv, int N,
+                                                      double *__restrict__ Z) {
+  extern __shared__ double ring[];   // D near slots, then the block's far_w far slots
+  double *far = ring + D * 256;
+  const int64_t lg = xcd_contiguous(blockIdx.x, gridDim.x);
+  const Block B = blocks[lg / ng];
+  const int cc = (int)(lg % ng);
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int colj = 16 * cc + c;
+  const bool colok = colj < N;
+  double *Zb = Z + B.row0 * N;
+  const int64_t *rp = rt_ptr + B.rt0;
+  const int lo = B.far_lo, Wf = B.far_w;
+  const bool from_mem = lo > D + 1;
+  // lane (q, c) reads and writes element (4r + q, c) of a Z tile (row 16R + 4r + q)
+  auto load_z = [&](int R, d4 &v) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * R + 4 * r + q;
+      v[r] = (R >= 0 && row < B.n && colok) ? Zb[(int64_t)row * N + colj] : 0.0;
+    }
+  };
+  auto load_ti = [&](int R, double(&ti)[4]) {
+    const double *Ti = tinv + (B.rt0 + R) * 256 + c * 16 + q;
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) ti[kc] = Ti[4 * kc];
+  };
+  d4 g, fz = d4{0.0, 0.0, 0.0, 0.0};
+  double ti[4];
+  load_z(0, g);
+  load_ti(0, ti);
+  if (Wf > 0 && from_mem) load_z(1 - lo, fz);
+  for (int R = 0; R < B.nrt; ++R) {
+    // the next row tile's G, inverse diagonal tile and far entry, one row tile ahead
+    d4 gn = d4{0.0, 0.0, 0.0, 0.0}, fzn = d4{0.0, 0.0, 0.0, 0.0};
+    double tin[4] = {0.0, 0.0, 0.0, 0.0};
+    if (R + 1 < B.nrt) {
+      load_z(R + 1, gn);
+      load_ti(R + 1, tin);
+      if (Wf > 0 && from_mem) load_z(R + 2 - lo, fzn);   // written at row tile R + 2 - lo <= R - 1
+    }
+    d4 a0 = g, a1 = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t t1 = rp[R + 1];
+    for (int64_t tb = rp[R]; tb < t1; tb += kGapBatch) {
+      d2 tl[kGapBatch], th[kGapBatch];
+      int cs[kGapBatch];
+#pragma unroll
+      for (int u = 0; u < kGapBatch; ++u) {
+        cs[u] = -1;
+        if (tb + u < t1) {   // uniform over the wavefront
+          cs[u] = rt_col[tb + u];
+          const d2 *Tt = (const d2 *)(tiles + (int64_t)rt_slot[tb + u] * 256 + c * 16 + 4 * q);   // A: T_RC(c, 4q + kc)
+          tl[u] = Tt[0];
+          th[u] = Tt[1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kGapBatch; ++u) {
+        if (cs[u] < 0) break;
+        const int C = cs[u];
+        const double *zr = (R - C <= D ? ring + (C % D) * 256 : far + (C % Wf) * 256) + 64 * q + c;   // B: Z_C(4q + kc, c)
+        a0 = mfma64(-tl[u][0], zr[0], a0);
+        a1 = mfma64(-th[u][0], zr[32], a1);
+        a0 = mfma64(-tl[u][1], zr[16], a0);
+        a1 = mfma64(-th[u][1], zr[48], a1);
+      }
+    }
+    // Z_R = T_RR^-1 (G_R - sum_C T_RC Z_C)
+    const d4 sum = a0 + a1;
+    d4 out = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) out = mfma64(ti[kc], sum[kc], out);
+    wave_lds_sync();   // every read of the slots rewritten below is done
+    const int Cf = R + 1 - lo;
+    if (Wf > 0 && Cf >= 0) {
+      double *fs = far + (Cf % Wf) * 256 + 16 * q + c;
+      if (from_mem) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fs[64 * r] = fz[r];
+      } else {   // Cf = R - D: the near slot that Z_R takes next
+        const double *ns = ring + (Cf % D) * 256 + 16 * q + c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fs[64 * r] = ns[64 * r];
+      }
+    }
+    double *slot = ring + (R % D) * 256 + 16 * q + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      slot[64 * r] = out[r];
+      const int row = 16 * R + 4 * r + q;
+      if (colok && row < B.n) Zb[(int64_t)row * N + colj] = out[r];
+    }
+    wave_lds_sync();
+    g = gn;
+    fz = fzn;
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) ti[kc] = tin[kc];
+  }
+}
+
 // X_a = X_b + Z on interior rows (each component has exactly one source row).
 template <typename TX, typename TO>
 __global__ __launch_bounds__(256) void k_mapback(const TX *__restrict__ Xb, int64_t ld,
@@ -994,7 +1116,22 @@ hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const
 #define FWD_NEAR(DD)                                                                                           \
   hipLaunchKernelGGL(k_fwd_sweep_near<DD>, dim3(nb * (unsigned)ng), dim3(64), 0, s, d.blocks, ng, d.rt_ptr,     \
                      d.rt_col, d.rt_slot, d.rt_nfar, d.tiles, d.tinv, p->N, out)
-  if (p->near_d < W) {   // far tiles exist: the split sweep
+  const size_t gap_bytes = (size_t)(p->near_d + p->far_w) * 2048;
+#define FWD_GAP(DD)                                                                                            \
+  hipLaunchKernelGGL(k_fwd_sweep_gap<DD>, dim3(nb * (unsigned)ng), dim3(64), gap_bytes, s, d.blocks, ng,       \
+                     d.rt_ptr, d.rt_col, d.rt_slot, d.tiles, d.tinv, p->N, out)
+  if (p->near_d < W && gap_bytes <= kGapRingMaxBytes) {   // far tiles within a small ring: the gap sweep
+    switch (p->near_d) {
+      case 1: FWD_GAP(1); break;
+      case 2: FWD_GAP(2); break;
+      case 3: FWD_GAP(3); break;
+      case 4: FWD_GAP(4); break;
+      case 5: FWD_GAP(5); break;
+      case 6: FWD_GAP(6); break;
+      case 7: FWD_GAP(7); break;
+      default: FWD_GAP(8); break;
+    }
+  } else if (p->near_d < W) {   // far tiles exist: the split sweep
     switch (p->near_d) {
       case 1: FWD_NEAR(1); break;
       case 2: FWD_NEAR(2); break;
@@ -1012,6 +1149,7 @@ hipError_t launch_fwd_sweep(enkfmc_plan *p, const Dev &d, const double *Q, const
     hipLaunchKernelGGL(k_fwd_sweep, dim3(nb, (unsigned)ng), dim3(64), 0, s, d.blocks, d.rt_ptr, d.rt_col, d.rt_slot,
                        d.tiles, d.tinv, p->N, out);
 #undef FWD_NEAR
+#undef FWD_GAP
   phase_end(p, ENKFMC_PH_SWEEP, s);
   return hipGetLastError();
 }

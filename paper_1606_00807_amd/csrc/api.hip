@@ -145,6 +145,10 @@ enkfmc_status enkfmc_plan_get_info(const enkfmc_plan *p, enkfmc_plan_info *info)
   info->f_entries = p->sum_F;
   info->s_entries = p->sum_S;
   info->factor_cache_bytes = factor_cache_bytes(p);
+  info->near_d = p->near_d;
+  info->far_lo = p->far_lo;
+  info->max_tile_distance = p->max_rt_back;
+  info->far_ring = p->far_w;
   return ENKFMC_OK;
 }
 

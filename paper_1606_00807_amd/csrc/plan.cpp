@@ -263,6 +263,23 @@ enkfmc_status build_plan(enkfmc_plan *p, const enkfmc_geometry *g, int32_t N, co
     int32_t d = 0;
     while (d + 1 < (int32_t)seen.size() && seen[(size_t)d + 1] && d < 8) ++d;
     p->near_d = std::max(d, 1);
+    // per block, the range of its distances beyond near_d
+    p->far_lo = 0;
+    p->far_w = 0;
+    for (Block &B : p->blocks) {
+      int32_t lo = 0, hi = 0;
+      for (int32_t R = 0; R < B.nrt; ++R)
+        for (int64_t t = p->rt_ptr[B.rt0 + R]; t < p->rt_ptr[B.rt0 + R + 1]; ++t) {
+          const int32_t e = R - p->rt_col[t];
+          if (e <= p->near_d) continue;
+          lo = lo == 0 ? e : std::min(lo, e);
+          hi = std::max(hi, e);
+        }
+      B.far_lo = lo;
+      B.far_w = lo > 0 ? hi - lo + 1 : 0;
+      if (lo > 0) p->far_lo = p->far_lo == 0 ? lo : std::min(p->far_lo, lo);
+      p->far_w = std::max(p->far_w, B.far_w);
+    }
     p->rt_nfar.assign((size_t)p->n_rt, 0);
     for (const Block &B : p->blocks)
       for (int32_t R = 0; R < B.nrt; ++R) {

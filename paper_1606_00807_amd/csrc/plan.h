@@ -28,6 +28,8 @@ struct Block {
   int32_t ldf;           // observation count rounded up to 16
   int64_t rt0;           // first row tile (global row-tile numbering)
   int64_t ot0;           // first observation tile (global numbering; ldf / 16 tiles)
+  int32_t far_lo;        // smallest distance R - C beyond the plan's near_d among the block's tiles (0: none)
+  int32_t far_w;         // the block's far range: far_lo .. far_lo + far_w - 1 holds its other distances
 };
 
 // Buckets of the batched fit: rows grouped by the kernel that fits them.
@@ -98,6 +100,8 @@ struct enkfmc_plan {
   int32_t max_rt_tiles = 0;
   int32_t max_rt_back = 0;     // largest R - C over the stored tiles T_RC (C < R) of any block
   int32_t near_d = 0;          // near distance of the split sweeps: the run 1..near_d of R - C values present
+  int32_t far_lo = 0;          // smallest R - C value beyond near_d over all blocks (0 if none)
+  int32_t far_w = 0;           // widest far range of a block (Block::far_w)
   int64_t n_fit = 0, nnz = 0, m_local = 0, sum_F = 0, sum_S = 0, sum_Q = 0;
   int32_t max_p = 0, max_bn = 0, max_bm = 0;
   enkfmc::Layout lay{};
