@@ -142,3 +142,38 @@ def test_factor_cache_sizes_and_validation():
     plan2 = Plan(geo, 40, np.array([1, 5, 9], np.int32))
     c2 = np.concatenate([plan2.row_counts(k) for k in range(int(plan2.info["n_subdomains"]))])
     assert np.all(c2 < 40) and plan2.info["factor_cache_bytes"] == _cache_bytes(c2, 40)
+
+
+def test_tile_distances_of_the_t63_pattern():
+    """The row-tile distances R - C of the stored tiles of T, which choose the
+    form of the triangular sweeps, worked out from the T-63 geometry (the
+    radius of influence that bounds each component's predecessors, Section
+    2.3: r_h = 4 points in each horizontal direction, r_v = 1 level).  A row tile is one latitude line of a 16-point box (16 rows), so
+    within a level the predecessors on lines y-1..y-4 lie 1..4 row tiles back;
+    on the level above they lie one level's line count back, +-4.  Boxes of
+    full 16 lines put them 12..20 back; the 12-line boxes at the poles (halo
+    cut on one side) 8..16 back."""
+    p = synth.make_t63()
+    info = Plan(p.geometry, p.N, p.obs_idx).info
+    assert info["near_d"] == 4
+    assert info["far_lo"] == 8
+    assert info["max_tile_distance"] == 20
+    assert info["far_ring"] == 9
+
+
+@pytest.mark.parametrize("geo", ["ring", "small_a", "small_b"])
+def test_tile_distance_fields_are_consistent(geo):
+    mk = {"ring": lambda: synth.make_ring(),
+          "small_a": lambda: synth.make_small(nx=14, ny=12, nlev=(3,), N=24, r_h=2, r_v=1, sdx=2, sdy=2,
+                                              obs_frac=0.3, config=301),
+          "small_b": lambda: synth.make_small(nx=16, ny=10, nlev=(3,), N=40, r_h=4, r_v=1, sdx=2, sdy=2,
+                                              obs_frac=0.3, config=302)}[geo]
+    p = mk()
+    info = Plan(p.geometry, p.N, p.obs_idx).info
+    nd, lo, hi, w = info["near_d"], info["far_lo"], info["max_tile_distance"], info["far_ring"]
+    assert 1 <= nd <= 8
+    assert (lo == 0) == (w == 0)
+    if lo:
+        assert nd < lo <= hi and 1 <= w <= hi - lo + 1
+    else:
+        assert hi <= nd
