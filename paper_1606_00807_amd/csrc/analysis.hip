@@ -306,6 +306,134 @@ __global__ __launch_bounds__(64) void k_bwd_sweep_ring(const Block *__restrict__
   }
 }
 
+// The same backward sweep with the gap ring of k_fwd_sweep_gap: LDS slots
+// only for the near run of distances 1..D (slot R mod D) and the block's far
+// range lo..hi (slot R mod Wf).  At the end of column tile C the tile that
+// enters the far range, F_{C-1+lo} (when it lies in the sweep, at or below
+// row tile Cs), goes into its slot: from the near ring when lo = D + 1 (the
+// tile F_C replaces), otherwise from memory, where this wavefront wrote it at
+// least two column tiles earlier; it is requested one column tile ahead.
+// Each column tile loads its own batch of T tiles (one batch of registers,
+// against two in k_bwd_sweep_ring), which with the smaller ring lets more
+// than one wavefront share a SIMD.
+template <int D>
+__global__ __launch_bounds__(64) void k_bwd_sweep_gap(const Block *__restrict__ blocks, int og,
+                                                      const int64_t *__restrict__ ct_ptr,
+                                                      const int32_t *__restrict__ ct_row,
+                                                      const int32_t *__restrict__ ct_slot,
+                                                      const int32_t *__restrict__ bobs_row,
+                                                      const int32_t *__restrict__ ot_jmax,
+                                                      const double *__restrict__ tiles,
+                                                      const double *__restrict__ tinv, double *__restrict__ F) {
+  extern __shared__ double ring[];   // D near slots, then the block's far_w far slots
+  double *far = ring + D * 256;
+  const int64_t lg = xcd_contiguous(blockIdx.x, gridDim.x);
+  const Block B = blocks[lg / og];
+  const int oc = (int)(lg % og);
+  if (16 * oc >= B.m) return;
+  const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
+  const int o = 16 * oc + c;
+  const int jo = o < B.m ? bobs_row[B.obs0 + o] : -1;
+  const int ldf = B.ldf;
+  const int lo = B.far_lo, Wf = B.far_w;
+  const bool from_mem = lo > D + 1;
+  double *Fb = F + B.F0;
+  const int Cs = ot_jmax[B.ot0 + oc] >> 4;
+  for (int C = B.nrt - 1; C > Cs; --C) {
+    double *Fc = Fb + (int64_t)(16 * C) * ldf + 16 * oc + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Fc[(int64_t)(4 * r + q) * ldf] = 0.0;
+  }
+  // lane (q, c) reads and writes element (4r + q, c) of an F tile
+  auto load_f = [&](int R, d4 &v) {
+    const double *Fr = Fb + (int64_t)(16 * R) * ldf + 16 * oc + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = (R <= Cs) ? Fr[(int64_t)(4 * r + q) * ldf] : 0.0;
+  };
+  auto zr_of = [&](int R, int C) {
+    return (R - C <= D ? ring + (R % D) * 256 : far + (R % Wf) * 256) + 16 * q + c;   // B operand: F_R(4kc + q, o)
+  };
+  const int64_t *cp = ct_ptr + B.rt0;
+  int Cl = Cs;
+  auto load_batch = [&](double(&tv)[kBwdBatch][4], int(&rs)[kBwdBatch], int &cnt) {
+    const int64_t s0 = cp[Cl];
+    int64_t s1 = cp[Cl + 1];
+    while (s1 > s0 && ct_row[s1 - 1] > Cs) --s1;
+    cnt = (int)(s1 - s0 < kBwdBatch ? s1 - s0 : kBwdBatch);
+#pragma unroll
+    for (int j = 0; j < kBwdBatch; ++j) {
+      if (j < cnt) {
+        const double *Tt = tiles + (int64_t)ct_slot[s0 + j] * 256 + q * 16 + c;   // A operand: T_RC(4kc + q, c)
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) tv[j][kc] = Tt[64 * kc];
+        rs[j] = ct_row[s0 + j];
+      }
+    }
+    --Cl;
+    return s1 - s0;
+  };
+  double ta[kBwdBatch][4];
+  int ra[kBwdBatch];
+  int na = 0;
+  d4 fz = d4{0.0, 0.0, 0.0, 0.0};   // far entry for the end of this column tile: F_{C-1+lo}
+  if (Wf > 0 && from_mem) load_f(Cs - 1 + lo, fz);
+  for (int C = Cs; C >= 0; --C) {
+    const int64_t fulla = load_batch(ta, ra, na);   // this column tile's own batch (one batch of registers)
+    d4 fzn = d4{0.0, 0.0, 0.0, 0.0};
+    if (Wf > 0 && from_mem && C > 0) load_f(C - 2 + lo, fzn);   // written at column tile C - 2 + lo >= C + 1
+    const double *Ti = tinv + (B.rt0 + C) * 256 + q * 16 + c;
+    double ti[4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) ti[kc] = Ti[64 * kc];
+    d4 acc0, acc1 = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc0[r] = (16 * C + 4 * r + q == jo) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < kBwdBatch; ++j) {
+      if (j < na) {
+        const double *fr = zr_of(ra[j], C);
+        acc0 = mfma64(-ta[j][0], fr[0], acc0);
+        acc1 = mfma64(-ta[j][2], fr[128], acc1);
+        acc0 = mfma64(-ta[j][1], fr[64], acc0);
+        acc1 = mfma64(-ta[j][3], fr[192], acc1);
+      }
+    }
+    // entries beyond the first batch of a long list: T from memory, F_R from the ring
+    for (int64_t t = cp[C] + kBwdBatch; t < cp[C] + fulla; ++t) {
+      const double *Tt = tiles + (int64_t)ct_slot[t] * 256 + q * 16 + c;
+      const double *fr = zr_of(ct_row[t], C);
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) acc0 = mfma64(-Tt[64 * kc], fr[64 * kc], acc0);
+    }
+    const d4 acc = acc0 + acc1;
+    d4 out = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) out = mfma64(ti[kc], acc[kc], out);
+    wave_lds_sync();   // every read of the slots rewritten below is done
+    const int Rf = C - 1 + lo;
+    if (Wf > 0 && C > 0 && Rf <= Cs) {
+      double *fs = far + (Rf % Wf) * 256 + 16 * q + c;
+      if (from_mem) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fs[64 * r] = fz[r];
+      } else {   // Rf = C + D: the near slot that F_C takes next
+        const double *ns = ring + (Rf % D) * 256 + 16 * q + c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fs[64 * r] = ns[64 * r];
+      }
+    }
+    double *slot = ring + (C % D) * 256 + 16 * q + c;
+    double *Fc = Fb + (int64_t)(16 * C) * ldf + 16 * oc + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      slot[64 * r] = out[r];
+      Fc[(int64_t)(4 * r + q) * ldf] = out[r];
+    }
+    wave_lds_sync();
+    fz = fzn;
+  }
+}
+
 // S = R + F^T D F (lower tiles, stride ldf); one wavefront per (block, tile
 // column J, chunk of up to 8 tile rows I >= J).
 __global__ __launch_bounds__(64) void k_dual_S(const Block *__restrict__ blocks, const int32_t *__restrict__ bobs_o,
@@ -1162,12 +1290,28 @@ hipError_t launch_dual_factor(enkfmc_plan *p, const Dev &d, const double *r_diag
   if (p->max_bm > 0) {
     phase_begin(p, ENKFMC_PH_DUAL_F, s);
     const int W = std::max(1, (int)p->max_rt_back);
-    if ((size_t)W * 2048 <= kRingMaxBytes)
+    const size_t gap_bytes = (size_t)(p->near_d + p->far_w) * 2048;
+#define BWD_GAP(DD)                                                                                            \
+  hipLaunchKernelGGL(k_bwd_sweep_gap<DD>, dim3(nb * oc), dim3(64), gap_bytes, s, d.blocks, (int)oc, d.ct_ptr,  \
+                     d.ct_row, d.ct_slot, d.bobs_row, d.ot_jmax, d.tiles, d.tinv, d.F)
+    if (p->near_d < W && gap_bytes <= kGapRingMaxBytes) {
+      switch (p->near_d) {
+        case 1: BWD_GAP(1); break;
+        case 2: BWD_GAP(2); break;
+        case 3: BWD_GAP(3); break;
+        case 4: BWD_GAP(4); break;
+        case 5: BWD_GAP(5); break;
+        case 6: BWD_GAP(6); break;
+        case 7: BWD_GAP(7); break;
+        default: BWD_GAP(8); break;
+      }
+    } else if ((size_t)W * 2048 <= kRingMaxBytes)
       hipLaunchKernelGGL(k_bwd_sweep_ring, dim3(nb * oc), dim3(64), (size_t)W * 2048, s, d.blocks, (int)oc, d.ct_ptr,
                          d.ct_row, d.ct_slot, d.bobs_row, d.ot_jmax, d.tiles, d.tinv, W, d.F);
     else
       hipLaunchKernelGGL(k_bwd_sweep, dim3(nb, oc), dim3(64), 0, s, d.blocks, d.ct_ptr, d.ct_row, d.ct_slot,
                          d.bobs_row, d.ot_jmax, d.tiles, d.tinv, d.F);
+#undef BWD_GAP
     phase_end(p, ENKFMC_PH_DUAL_F, s);
     phase_begin(p, ENKFMC_PH_DUAL_S, s);
     hipLaunchKernelGGL(k_dual_S, dim3(nb, oc, (oc + 7) / 8), dim3(64), 0, s, d.blocks, d.bobs_o, d.ot_jmax, d.F,
