@@ -1058,7 +1058,6 @@ __global__ __launch_bounds__(64) void k_fwd_sweep_near(const Block *__restrict__
 // wavefront per (block, member tile), numbered so that the member tiles of a
 // block share its T tiles in L2.
 constexpr int kGapBatch = 12;
-constexpr size_t kGapRingMaxBytes = 32 * 1024;
 
 template <int D>
 __global__ __launch_bounds__(64) void k_fwd_sweep_gap(const Block *__restrict__ blocks, int ng,

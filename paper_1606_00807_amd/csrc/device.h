@@ -127,6 +127,9 @@ constexpr int kXcds = 8;
 // Largest ring of 16x16 tiles a triangular sweep keeps in LDS (one
 // workgroup's dynamic LDS); plans that need more use the sweeps without one.
 constexpr size_t kRingMaxBytes = 64 * 1024;
+// Largest gap ring (the near run and a block's far range of tiles) of the
+// triangular sweeps.
+constexpr size_t kGapRingMaxBytes = 32 * 1024;
 __device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G) {
   const int64_t x = b % kXcds, s = b / kXcds, q = G / kXcds, rm = G % kXcds;
   return x < rm ? x * (q + 1) + s : rm * (q + 1) + (x - rm) * q + s;
