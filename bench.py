@@ -139,7 +139,7 @@ def adjoint_roofline(info, N, counts, phases, fit_all_flops, cached=False):
 # counters, each scaled by what the same counter reads for a plain copy of
 # known size.  Valid only for the kernel source it was taken on: a changed
 # source reports null.
-TRAFFIC = {"fit_batched_sha256": "ee19d4f1e9d04145f917801523f767900794e30e5fa0bdb26bf0741ac4d6809e",
+TRAFFIC = {"fit_batched_sha256": "a375cf2eac204ffb77bb184c0fbf3bb488af1ee3e4c3a0589ede221558d9fc4c",
            "fetch_bytes": 1.7701e+09, "write_bytes": 2.0802e+09, "bytes_per_launch": 3.8503e+09,
            "fetch_scale": 1.9999, "write_scale": 1.0}
 
