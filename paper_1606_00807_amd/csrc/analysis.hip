@@ -435,37 +435,56 @@ __global__ __launch_bounds__(64) void k_bwd_sweep_gap(const Block *__restrict__ 
 }
 
 // S = R + F^T D F (lower tiles, stride ldf); one wavefront per (block, tile
-// column J, chunk of up to 8 tile rows I >= J).
-__global__ __launch_bounds__(64) void k_dual_S(const Block *__restrict__ blocks, const int32_t *__restrict__ bobs_o,
+// column J, chunk of up to 8 tile rows I >= J), on a one-dimensional grid
+// numbered so that the wavefronts of a block run on one XCD and share its F
+// in L2.  The loads of k-step ks + 1 are issued before the products of ks.
+constexpr int kDualSTiles = 8;
+
+__global__ __launch_bounds__(64) void k_dual_S(const Block *__restrict__ blocks, int oc,
+                                               const int32_t *__restrict__ bobs_o,
                                                const int32_t *__restrict__ ot_jmax, const double *__restrict__ F,
                                                const double *__restrict__ dvec, const double *__restrict__ r_diag,
                                                double *__restrict__ S) {
-  constexpr int kMaxTiles = 8;
-  const Block B = blocks[blockIdx.x];
-  const int J = blockIdx.y;
+  int b, jt;
+  block_tile(oc * ((oc + kDualSTiles - 1) / kDualSTiles), b, jt);
+  const Block B = blocks[b];
+  const int J = jt % oc;
   const int TJ = B.ldf >> 4;
-  const int I0 = J + kMaxTiles * (int)blockIdx.z;
+  const int I0 = J + kDualSTiles * (jt / oc);
   if (J >= TJ || I0 >= TJ) return;
   const int lane = threadIdx.x, q = lane >> 4, c = lane & 15;
   const int ldf = B.ldf;
   const double *Fb = F + B.F0;
-  d4 acc[kMaxTiles];
+  d4 acc[kDualSTiles];
 #pragma unroll
-  for (int I = 0; I < kMaxTiles; ++I) acc[I] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int I = 0; I < kDualSTiles; ++I) acc[I] = d4{0.0, 0.0, 0.0, 0.0};
   // column tile J of F is zero below its largest observed row
   const int ksteps = (ot_jmax[B.ot0 + J] >> 2) + 1;
-  for (int ks = 0; ks < ksteps; ++ks) {
+  auto load = [&](int ks, double &bv, double(&fv)[kDualSTiles]) {
     const int k = 4 * ks + q;
     const double dk = k < B.n ? dvec[B.row0 + k] : 0.0;
     const double *Fk = Fb + (int64_t)k * ldf + c;
-    const double b = dk * Fk[16 * J];
+    bv = dk * Fk[16 * J];
 #pragma unroll
-    for (int i = 0; i < kMaxTiles; ++i)
-      if (I0 + i < TJ) acc[i] = mfma64(Fk[16 * (I0 + i)], b, acc[i]);
+    for (int i = 0; i < kDualSTiles; ++i) fv[i] = I0 + i < TJ ? Fk[16 * (I0 + i)] : 0.0;
+  };
+  double bc, fc[kDualSTiles];
+  load(0, bc, fc);
+  for (int ks = 0; ks < ksteps; ++ks) {
+    double bn = 0.0, fn[kDualSTiles];
+#pragma unroll
+    for (int i = 0; i < kDualSTiles; ++i) fn[i] = 0.0;
+    if (ks + 1 < ksteps) load(ks + 1, bn, fn);
+#pragma unroll
+    for (int i = 0; i < kDualSTiles; ++i)
+      if (I0 + i < TJ) acc[i] = mfma64(fc[i], bc, acc[i]);
+    bc = bn;
+#pragma unroll
+    for (int i = 0; i < kDualSTiles; ++i) fc[i] = fn[i];
   }
   double *Sb = S + B.S0;
 #pragma unroll
-  for (int i = 0; i < kMaxTiles; ++i) {
+  for (int i = 0; i < kDualSTiles; ++i) {
     const int I = I0 + i;
     if (I < TJ) {
 #pragma unroll
@@ -705,8 +724,9 @@ hipError_t launch_adj_solve_S_tiles(enkfmc_plan *p, const Dev &d, double *P, hip
 // G = D (F Q) of row tile R (or D (V - F Q) with V given), written into the
 // output rows that the forward sweep then solves in place.  One wavefront per
 // (block, row tile).  Each F fragment it loads feeds up to kGTiles 16-member
-// column tiles at once, so F_R is read once per kGTiles member tiles (the
-// launch is bound by HBM traffic, most of it re-reads of F).
+// column tiles at once, so F_R is read once per kGTiles member tiles.  (A
+// one-dimensional grid with the row tiles of a block on one XCD, as in
+// k_dual_S, was slower here: 1.37 ms against 1.30 at T-63.)
 constexpr int kGTiles = 5;
 
 __global__ __launch_bounds__(64) void k_dual_G(const Block *__restrict__ blocks, const int32_t *__restrict__ ot_jmax,
@@ -1313,8 +1333,8 @@ hipError_t launch_dual_factor(enkfmc_plan *p, const Dev &d, const double *r_diag
 #undef BWD_GAP
     phase_end(p, ENKFMC_PH_DUAL_F, s);
     phase_begin(p, ENKFMC_PH_DUAL_S, s);
-    hipLaunchKernelGGL(k_dual_S, dim3(nb, oc, (oc + 7) / 8), dim3(64), 0, s, d.blocks, d.bobs_o, d.ot_jmax, d.F,
-                       d.dvec, r_diag, d.S);
+    hipLaunchKernelGGL(k_dual_S, dim3(nb * oc * ((oc + kDualSTiles - 1) / kDualSTiles)), dim3(64), 0, s, d.blocks,
+                       (int)oc, d.bobs_o, d.ot_jmax, d.F, d.dvec, r_diag, d.S);
     phase_end(p, ENKFMC_PH_DUAL_S, s);
     phase_begin(p, ENKFMC_PH_DUAL_CHOL, s);
     if (dual_chol_tiles_fit(p)) {
