@@ -1077,7 +1077,7 @@ __global__ __launch_bounds__(64) void k_fwd_sweep_near(const Block *__restrict__
 // tile and the far entry of the next row tile load one row tile ahead.  One
 // wavefront per (block, member tile), numbered so that the member tiles of a
 // block share its T tiles in L2.
-constexpr int kGapBatch = 12;
+constexpr int kGapBatch = 16;
 
 template <int D>
 __global__ __launch_bounds__(64) void k_fwd_sweep_gap(const Block *__restrict__ blocks, int ng,
