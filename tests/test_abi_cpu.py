@@ -177,3 +177,47 @@ def test_tile_distance_fields_are_consistent(geo):
         assert nd < lo <= hi and 1 <= w <= hi - lo + 1
     else:
         assert hi <= nd
+
+
+def _oracle_tile_distances(geo, obs):
+    """near_d, far_lo, largest distance and widest per-block far range, from
+    the oracle's predecessor pattern: a block is one variable's rows of a
+    sub-domain (contiguous in local order), its row tiles 16 consecutive rows,
+    and a stored tile T_RC (C < R) is any (row tile, column tile) pair that
+    holds a predecessor entry."""
+    var_off = np.cumsum([0] + [nl * geo["nx"] * geo["ny"] for nl in geo["nlev"]])
+    blocks = []
+    for k in range(G.n_subdomains(geo)):
+        pat = G.subdomain_pattern(geo, k, obs)
+        var = np.searchsorted(var_off, pat.loc2glob, side="right") - 1
+        start = {int(v): int(np.argmax(var == v)) for v in np.unique(var)}
+        for v, s0 in start.items():
+            dists = set()
+            for i in np.nonzero(var == v)[0]:
+                for j in pat.col_idx[pat.row_ptr[i]:pat.row_ptr[i + 1]]:
+                    assert var[j] == v
+                    d = (int(i) - s0) // 16 - (int(j) - s0) // 16
+                    if d > 0:
+                        dists.add(d)
+            blocks.append(dists)
+    union = set().union(*blocks)
+    near = 0
+    while near + 1 in union and near < 8:
+        near += 1
+    near = max(near, 1)
+    far = [sorted(e for e in b if e > near) for b in blocks]
+    los = [f[0] for f in far if f]
+    return near, min(los, default=0), max(union, default=0), max((f[-1] - f[0] + 1 for f in far if f), default=0)
+
+
+@pytest.mark.parametrize("geo", [
+    synth.geometry(32, 20, [3], True, 2, 1, 2, 1),
+    synth.geometry(40, 24, [2, 1], False, 2, 2, 3, 1),
+    synth.geometry(24, 40, [4], True, 1, 2, 1, 1),
+])
+def test_tile_distance_fields_match_the_oracle_pattern(geo):
+    n = synth.state_size(geo)
+    obs = synth.random_sites(n, n // 4, synth.rng(11, 2))
+    info = Plan(geo, 12, obs).info
+    got = (info["near_d"], info["far_lo"], info["max_tile_distance"], info["far_ring"])
+    assert got == _oracle_tile_distances(geo, obs)
